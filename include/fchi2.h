@@ -1,0 +1,182 @@
+/*
+ * fchi2.h - C ABI of the MI355X (gfx950) F-chi2 period-search library.
+ *
+ * The library computes, for irregularly sampled data (t_i, x_i, sigma_i), the
+ * chi2 reduction obtained by fitting a Fourier series truncated at H'
+ * harmonics (Palmer, Fast chi2 period search, eq. eqtrunc and eq. eqchigen),
+ * minimised over its 2H'+1 linear coefficients at every trial frequency of a
+ * dense grid, for every H' = 1..H at once (Section 1: evaluations for several
+ * H share their stages):
+ *
+ *   Delta chi2(f_k, H') = chi2_0 - min_A sum_i w_i (x_i - Phi_H'(A, f_k, t_i))^2
+ *                       = beta^T alpha^-1 beta                      (eq. eqchix)
+ *
+ * with w_i = sigma_i^-2, chi2_0 = sum_i w_i (x_i - xbar)^2, xbar the weighted
+ * mean (Section 3b and 3d), f_k = k * f_max / n_freq for k = 0..n_freq-1.
+ * alpha and beta are built from the transforms P(f), Q(f) of the weighted data
+ * and the weights (eq. eqPQ) by product-to-sum identities (Section 2), the
+ * transforms are computed with FFTs (Section 3b), and the normal equations are
+ * solved per frequency (Section 3c, 3d).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named "device" point to GPU memory on the current HIP device;
+ *    "host" pointers to host memory.  The caller owns every buffer; the
+ *    library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued on it; no call synchronises the stream, except
+ *    fchi2_plan, which initialises plan tables and returns after they are
+ *    ready.
+ *  - fchi2_search, fchi2_backward and fchi2_top_peaks allocate no memory and
+ *    make no blocking call, so they may be captured in a HIP graph.
+ *  - Errors are reported by the return code only (no exceptions, no abort);
+ *    fchi2_last_error() gives a message for the calling thread.  Argument
+ *    errors are detected on the host before any device work is enqueued.
+ *  - Per-curve data errors (non-finite values, sigma <= 0, unsorted t, an
+ *    empty curve, or a span too long for the frequency grid) do not fail the
+ *    call: that curve's outputs become NaN and its flag bytes carry the
+ *    FCHI2_CURVE_* bits; other curves are unaffected.
+ *  - A plan must not be used by two threads at once.
+ */
+#ifndef FCHI2_H_
+#define FCHI2_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fchi2_plan_s* fchi2_plan_t;
+
+typedef enum {
+  FCHI2_OK = 0,
+  FCHI2_ERR_ARG = 1,          /* invalid argument (message says which)       */
+  FCHI2_ERR_NOMEM = 2,        /* plan-table allocation failed                */
+  FCHI2_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed  */
+  FCHI2_ERR_STATE = 4,        /* call not valid for this plan's flags/state  */
+  FCHI2_ERR_UNSUPPORTED = 5   /* size or parameter outside what is built     */
+} fchi2_status_t;
+
+typedef enum {
+  FCHI2_FP64 = 0,   /* FP64 spreading, FFT, assembly and solve                */
+  FCHI2_MIXED = 1   /* FP64 phase reduction, moments and solve; FP32 grids,
+                       FFT and spectra; FP32 Delta chi2 output               */
+} fchi2_precision_t;
+
+/* Plan flags. */
+#define FCHI2_KEEP_FOR_BACKWARD 1u /* keep all spectra in the workspace      */
+#define FCHI2_GRAPH 2u             /* replay searches through a HIP graph    */
+
+/* Largest H supported. */
+#define FCHI2_H_MAX 8
+
+/* Per-bin flag bits (flags output of fchi2_search). */
+#define FCHI2_BIN_PIVOT 1u   /* a pivot of the normal matrix was dropped      */
+#define FCHI2_BIN_LOW_F 2u   /* f_k < 1 / span (variability, not periodicity) */
+#define FCHI2_BIN_DC 4u      /* k = 0; Delta chi2 is defined as 0             */
+/* Per-curve bits (set in every flag byte of a rejected curve). */
+#define FCHI2_CURVE_NONFINITE 8u   /* non-finite t/x/sigma or sigma <= 0     */
+#define FCHI2_CURVE_UNSORTED 16u   /* t not ascending within the curve       */
+#define FCHI2_CURVE_WRAP 32u       /* 2H * span * f_max / n_freq too large   */
+#define FCHI2_CURVE_FEW 64u        /* fewer than 2H+1 points (not fatal)     */
+#define FCHI2_CURVE_EMPTY 128u     /* no points                               */
+
+typedef struct {
+  int32_t n_curves;          /* >= 1                                          */
+  const int64_t* offsets;    /* host, n_curves+1 CSR offsets into t/x/sigma,
+                                offsets[0] = 0, nondecreasing; copied by
+                                fchi2_plan                                     */
+  double f_max;              /* > 0: bins f_k = k f_max / n_freq, k < n_freq  */
+  int32_t H;                 /* 1 .. FCHI2_H_MAX                              */
+  int64_t n_freq;            /* power of two, 2^10 .. 2^24                    */
+  int32_t precision;         /* fchi2_precision_t                             */
+  uint32_t flags;            /* FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH         */
+  int32_t kernel_width;      /* spreading kernel taps, 0 = default
+                                (14 for FP64, 8 for MIXED); 4..16             */
+  int32_t curves_per_wave;   /* curves transformed together; 0 = automatic   */
+} fchi2_plan_desc_t;
+
+/*
+ * Create a plan.  Validates `desc`, derives the grid geometry (grid length
+ * L = 4 n_freq cells per harmonic grid, Section 3b's zero-padded arrays that
+ * cover at least 2H times the observed span), the FFT pass split and the
+ * spreading kernel, and builds its device tables (twiddles, deconvolution) on
+ * `stream`, waiting for them.  Allocates device memory for those tables
+ * (owned by the plan).  On success *out receives the plan.
+ * Errors: FCHI2_ERR_ARG (bad desc or NULL out), FCHI2_ERR_UNSUPPORTED,
+ * FCHI2_ERR_NOMEM, FCHI2_ERR_HIP.
+ */
+fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_plan_t* out);
+
+/* Bytes of device workspace fchi2_search / fchi2_backward need (0 for NULL). */
+size_t fchi2_workspace_bytes(fchi2_plan_t plan);
+
+/* Total number of points (offsets[n_curves]) of the plan. */
+int64_t fchi2_total_points(fchi2_plan_t plan);
+
+/*
+ * Delta chi2 for all curves, bins and H' = 1..H (Sections 3b-3d).
+ *  t, x, sigma  device FP64 [n_total] in the plan's CSR layout; t ascending
+ *               within each curve (unsorted curves are flagged)
+ *  workspace    device, >= fchi2_workspace_bytes(plan) bytes, 256-byte
+ *               aligned; its contents are overwritten (and, with
+ *               FCHI2_KEEP_FOR_BACKWARD, read by fchi2_backward)
+ *  dchi2        device [n_curves][H][n_freq], row h holds H' = h + 1;
+ *               double for FCHI2_FP64, float for FCHI2_MIXED
+ *  chi2_0       device FP64 [n_curves] or NULL
+ *  flags        device uint8 [n_curves][n_freq] (FCHI2_BIN_* / FCHI2_CURVE_*)
+ *               or NULL
+ * Errors: FCHI2_ERR_ARG (NULL plan/pointer, misaligned or small workspace),
+ * FCHI2_ERR_HIP.
+ */
+fchi2_status_t fchi2_search(fchi2_plan_t plan, const double* t, const double* x,
+                            const double* sigma, void* workspace, size_t workspace_bytes,
+                            void* dchi2, double* chi2_0, uint8_t* flags, void* stream);
+
+/*
+ * Gradient of a scalar loss through Delta chi2 (adjoint of the whole chain:
+ * solve, assembly, deconvolution, FFT and spreading, then the weighted mean;
+ * derived from eq. eqchigen and eq. eqchix).
+ *  grad_dchi2   device, same layout and type as dchi2 of fchi2_search:
+ *               dLoss/dDelta chi2(k, H')
+ *  grad_x       device FP64 [n_total]: dLoss/dx_i (overwritten)
+ *  grad_sigma   device FP64 [n_total]: dLoss/dsigma_i (overwritten)
+ * The plan must have FCHI2_KEEP_FOR_BACKWARD and fchi2_search must have run
+ * on the same inputs and workspace (else FCHI2_ERR_STATE).  Rejected curves
+ * get NaN gradients.
+ */
+fchi2_status_t fchi2_backward(fchi2_plan_t plan, const double* t, const double* x,
+                              const double* sigma, const void* grad_dchi2, void* workspace,
+                              size_t workspace_bytes, double* grad_x, double* grad_sigma,
+                              void* stream);
+
+/*
+ * Indices of the K largest strict local maxima of row `hrow` (H' = hrow + 1)
+ * of each curve's Delta chi2 (the best frequencies, Section 3e): bins k in
+ * [k_lo, n_freq - 2] with D[k] > D[k-1] and D[k] >= D[k+1], ordered by value,
+ * ties to the lower k; missing entries are -1.
+ *  dchi2     device, as written by fchi2_search
+ *  scratch   device, >= fchi2_top_peaks_scratch_bytes(plan, K) bytes
+ *  out_idx   device int64 [n_curves][K]
+ * Errors: FCHI2_ERR_ARG (K outside 1..64, bad hrow or k_lo, NULL), FCHI2_ERR_HIP.
+ */
+size_t fchi2_top_peaks_scratch_bytes(fchi2_plan_t plan, int32_t K);
+fchi2_status_t fchi2_top_peaks(fchi2_plan_t plan, const void* dchi2, int32_t hrow, int64_t k_lo,
+                               int32_t K, void* scratch, size_t scratch_bytes, int64_t* out_idx,
+                               void* stream);
+
+/* Free the plan and its device tables (no-op for NULL). */
+void fchi2_destroy(fchi2_plan_t plan);
+
+/* Static description of a status code. */
+const char* fchi2_status_string(fchi2_status_t status);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* fchi2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCHI2_H_ */

@@ -1,0 +1,441 @@
+// Adjoint of the search: gradient of a scalar loss L through Delta chi2 with
+// respect to x_i and sigma_i.
+//
+// Per bin, Delta(H') = beta' alpha'^-1 beta' on the leading (2H'+1) block
+// (eq. eqchix), so with A' = alpha'^-1 beta' (eq. eqcoeffs):
+//   dDelta(H')/dbeta = 2 A',  dDelta(H')/dalpha = -A' A'^T.
+// A' comes from the forward Cholesky factor by back substitution with its
+// leading block.  The product-to-sum assembly (Section 2) is transposed onto
+// the gradients of Re/Im Q(m f) and P(m f); the deconvolution factor and the
+// unpacking of the packed grids are transposed; an FFT of the conjugated
+// adjoint spectrum gives the conjugated grid gradient (the adjoint of the
+// +i transform is the -i transform); and interpolation with the same kernel
+// at the same positions (the transpose of the spreading) gives per-point
+// gradients g_q (strength w) and g_p (strength w (x - xbar)).  Finally,
+// with xbar = sum w x / W:
+//   dL/dx_i     = w_i (g_p,i - gbar_p),  gbar_p = sum_j w_j g_p,j / W
+//   dL/dw_i     = g_q,i + dL/dW + (x_i - xbar)(g_p,i - gbar_p)
+//   dL/dsigma_i = -2 w_i / sigma_i * dL/dw_i
+// where dL/dW collects the alpha entries that equal W = Q(0).
+#include <cmath>
+
+#include "fchi2_internal.h"
+#include "launch.h"
+
+namespace fchi2 {
+
+namespace {
+
+constexpr int kNT = 256;
+
+template <int H>
+struct Layout {
+  static constexpr int P = H + (H + 1) / 2;
+};
+
+__device__ __forceinline__ double Cp(const double* Qr, int gd) { return Qr[gd < 0 ? -gd : gd]; }
+__device__ __forceinline__ double Sp(const double* Qi, int gd) {
+  return gd < 0 ? -Qi[-gd] : Qi[gd];
+}
+
+__device__ __forceinline__ double alpha_ij(int i, int j, const double* Qr, const double* Qi) {
+  if (j == 0) {
+    if (i == 0) return Qr[0];
+    const int h = (i + 1) >> 1;
+    return (i & 1) ? Qi[h] : Qr[h];
+  }
+  const int h = (i + 1) >> 1, hp = (j + 1) >> 1;
+  const bool si = (i & 1), sj = (j & 1);
+  if (si && sj) return 0.5 * (Cp(Qr, h - hp) - Cp(Qr, h + hp));
+  if (si && !sj) return 0.5 * (Sp(Qi, h + hp) + Sp(Qi, h - hp));
+  if (!si && sj) return 0.5 * (Sp(Qi, h + hp) - Sp(Qi, h - hp));
+  return 0.5 * (Cp(Qr, h - hp) + Cp(Qr, h + hp));
+}
+
+__device__ __forceinline__ double beta_i(int i, const double* Pr, const double* Pi) {
+  if (i == 0) return 0.0;
+  const int h = (i + 1) >> 1;
+  return (i & 1) ? Pi[h] : Pr[h];
+}
+
+// Add v * d alpha_ij / d(Q) for i >= j into dQr/dQi (index 0 of dQr is dW).
+__device__ __forceinline__ void alpha_adj(int i, int j, double v, double* dQr, double* dQi) {
+  if (j == 0) {
+    if (i == 0) {
+      dQr[0] += v;
+      return;
+    }
+    const int h = (i + 1) >> 1;
+    if (i & 1) dQi[h] += v;
+    else dQr[h] += v;
+    return;
+  }
+  const int h = (i + 1) >> 1, hp = (j + 1) >> 1;  // h >= hp for i >= j
+  const int gm = h - hp, gpl = h + hp;
+  const double hv = 0.5 * v;
+  const bool si = (i & 1), sj = (j & 1);
+  if (si && sj) {
+    dQr[gm] += hv;
+    dQr[gpl] -= hv;
+  } else if (si && !sj) {
+    dQi[gpl] += hv;
+    if (gm > 0) dQi[gm] += hv;
+  } else if (!si && sj) {
+    dQi[gpl] += hv;
+    if (gm > 0) dQi[gm] -= hv;
+  } else {
+    dQr[gm] += hv;
+    dQr[gpl] += hv;
+  }
+}
+
+template <int H, typename R, typename O>
+__global__ __launch_bounds__(kNT) void k_adjoint(const cplx<R>* __restrict__ zc,
+                                                 const cplx<R>* __restrict__ D,
+                                                 const Moments* __restrict__ mom, Geom g,
+                                                 int curve0, double eps,
+                                                 const O* __restrict__ gin,
+                                                 cplx<R>* __restrict__ spec,
+                                                 double* __restrict__ dw_part, int bpc) {
+  constexpr int d = 2 * H + 1;
+  constexpr int P = Layout<H>::P;
+  __shared__ double red[kNT];
+  const int64_t nf = g.n_freq;
+  const int64_t L = g.L;
+  const int tid = threadIdx.x;
+  const int64_t k = (int64_t)blockIdx.x * kNT + tid;
+  const int cw = blockIdx.y;
+  const int c = curve0 + cw;
+  const Moments mo = mom[c];
+  if (mo.flags & kCurveFatal) return;  // whole block: uniform per curve
+  cplx<R>* sp = spec + (int64_t)cw * P * L;
+  const cplx<R> zero = cmk<R>((R)0, (R)0);
+  double dW = 0.0;
+
+  if (k < nf) {
+    if (k == 0) {
+      for (int pp = 0; pp < P; ++pp) {
+        sp[pp * L + 0] = zero;
+        sp[pp * L + (L - nf)] = zero;
+      }
+    } else {
+      // Forward spectra at bin k (same unpacking as the solve).
+      double Qr[2 * H + 1], Qi[2 * H + 1], Pr[H + 1], Pi[H + 1];
+      const cplx<R> Dk = D[k];
+      const double Dr = (double)Dk.x, Di = (double)Dk.y;
+      Qr[0] = mo.W;
+      Qi[0] = 0.0;
+      Pr[0] = 0.0;
+      Pi[0] = 0.0;
+#pragma unroll
+      for (int pp = 0; pp < P; ++pp) {
+        const cplx<R> z0 = zc[(((int64_t)cw * P + pp) * 2 + 0) * nf + k];
+        const cplx<R> z1 = zc[(((int64_t)cw * P + pp) * 2 + 1) * nf + k];
+        const double ax = 0.5 * ((double)z0.x + (double)z1.x);
+        const double ay = 0.5 * ((double)z0.y - (double)z1.y);
+        const double bx = 0.5 * ((double)z0.y + (double)z1.y);
+        const double by = -0.5 * ((double)z0.x - (double)z1.x);
+        const double Ar = ax * Dr - ay * Di, Ai = ax * Di + ay * Dr;
+        const double Br = bx * Dr - by * Di, Bi = bx * Di + by * Dr;
+        if (pp < H) {
+          Qr[2 * pp + 1] = Ar;
+          Qi[2 * pp + 1] = Ai;
+          Qr[2 * pp + 2] = Br;
+          Qi[2 * pp + 2] = Bi;
+        } else {
+          const int j = pp - H;
+          Pr[2 * j + 1] = Ar;
+          Pi[2 * j + 1] = Ai;
+          if (2 * j + 2 <= H) {
+            Pr[2 * j + 2] = Br;
+            Pi[2 * j + 2] = Bi;
+          }
+        }
+      }
+      // Cholesky with the forward's pivot rule.
+      double Lm[d][d];
+      double inv[d];
+      double z[d];
+#pragma unroll
+      for (int i = 0; i < d; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+          double s = alpha_ij(i, j, Qr, Qi);
+#pragma unroll
+          for (int l = 0; l < j; ++l) s -= Lm[i][l] * Lm[j][l];
+          if (i == j) {
+            const double ajj = alpha_ij(i, i, Qr, Qi);
+            if (s > eps * ajj && s > 0.0) {
+              const double r = sqrt(s);
+              Lm[i][i] = r;
+              inv[i] = 1.0 / r;
+            } else {
+              Lm[i][i] = 0.0;
+              inv[i] = 0.0;
+            }
+          } else {
+            Lm[i][j] = s * inv[j];
+          }
+        }
+        double s = beta_i(i, Pr, Pi);
+#pragma unroll
+        for (int l = 0; l < i; ++l) s -= Lm[i][l] * z[l];
+        z[i] = s * inv[i];
+      }
+      // Accumulate dQ (index 0 = dW) and dP over H' = 1..H.
+      double dQr[2 * H + 1], dQi[2 * H + 1], dPr[H + 1], dPi[H + 1];
+#pragma unroll
+      for (int m = 0; m <= 2 * H; ++m) {
+        dQr[m] = 0.0;
+        dQi[m] = 0.0;
+      }
+#pragma unroll
+      for (int m = 0; m <= H; ++m) {
+        dPr[m] = 0.0;
+        dPi[m] = 0.0;
+      }
+      const O* gk = gin + (int64_t)c * H * nf + k;
+#pragma unroll
+      for (int hp = 1; hp <= H; ++hp) {
+        const double gv = (double)gk[(hp - 1) * nf];
+        const int dp = 2 * hp + 1;
+        double A[d];
+#pragma unroll
+        for (int ii = d - 1; ii >= 0; --ii) {
+          if (ii < dp) {
+            double s = z[ii];
+#pragma unroll
+            for (int l = ii + 1; l < d; ++l)
+              if (l < dp) s -= Lm[l][ii] * A[l];
+            A[ii] = s * inv[ii];
+          }
+        }
+#pragma unroll
+        for (int i = 1; i < d; ++i) {
+          if (i < dp) {
+            const double db = 2.0 * gv * A[i];
+            const int h = (i + 1) >> 1;
+            if (i & 1) dPi[h] += db;
+            else dPr[h] += db;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < d; ++i) {
+#pragma unroll
+          for (int j = 0; j <= i; ++j) {
+            if (i < dp) {
+              const double v = -gv * A[i] * A[j] * (i == j ? 1.0 : 2.0);
+              alpha_adj(i, j, v, dQr, dQi);
+            }
+          }
+        }
+      }
+      dW = dQr[0];
+      // Transpose of D and of the unpacking; write the conjugated adjoint
+      // spectrum at k and L - k of every packed grid.
+#pragma unroll
+      for (int pp = 0; pp < P; ++pp) {
+        double gar, gai, gbr, gbi;
+        if (pp < H) {
+          gar = dQr[2 * pp + 1];
+          gai = dQi[2 * pp + 1];
+          gbr = dQr[2 * pp + 2];
+          gbi = dQi[2 * pp + 2];
+        } else {
+          const int j = pp - H;
+          gar = dPr[2 * j + 1];
+          gai = dPi[2 * j + 1];
+          gbr = (2 * j + 2 <= H) ? dPr[2 * j + 2] : 0.0;
+          gbi = (2 * j + 2 <= H) ? dPi[2 * j + 2] : 0.0;
+        }
+        // G_tilde = conj(D) * G
+        const double tar = gar * Dr + gai * Di, tai = gai * Dr - gar * Di;
+        const double tbr = gbr * Dr + gbi * Di, tbi = gbi * Dr - gbr * Di;
+        // G_z0 = G_a/2 + (i/2) G_b ; G_z1 = conj(G_a)/2 + (i/2) conj(G_b)
+        const double z0r = 0.5 * tar - 0.5 * tbi, z0i = 0.5 * tai + 0.5 * tbr;
+        const double z1r = 0.5 * tar + 0.5 * tbi, z1i = -0.5 * tai + 0.5 * tbr;
+        sp[pp * L + k] = cmk<R>((R)z0r, (R)(-z0i));
+        sp[pp * L + (L - k)] = cmk<R>((R)z1r, (R)(-z1i));
+      }
+    }
+  }
+  // Block sum of dW (deterministic tree).
+  red[tid] = dW;
+  __syncthreads();
+  for (int s = kNT / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) dw_part[(int64_t)c * bpc + blockIdx.x] = red[0];
+}
+
+template <typename R>
+__device__ __forceinline__ R es_kernel(R z, R beta) {
+  const R q = (R)1 - z * z;
+  if (!(q > (R)0)) return (R)0;
+  if constexpr (sizeof(R) == 4) {
+    return expf(beta * (sqrtf(q) - 1.0f));
+  } else {
+    return exp(beta * (sqrt(q) - 1.0));
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kNT) void k_gather(const double* __restrict__ t,
+                                                const Moments* __restrict__ mom, Geom g,
+                                                int curve0, const cplx<R>* __restrict__ grid,
+                                                double* __restrict__ gq, double* __restrict__ gp) {
+  const int cw = blockIdx.y;
+  const Moments mo = mom[curve0 + cw];
+  const int64_t il = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (il >= mo.n) return;
+  if (mo.flags & kCurveFatal) return;
+  const int64_t i = mo.start + il;
+  const int hw = g.w / 2;
+  const R two_over_w = (R)(2.0 / (double)g.w);
+  const R beta = (R)g.beta;
+  const double v = (t[i] - mo.T0) * g.df;
+  R aq = (R)0, ap = (R)0;
+  for (int p = 0; p < g.P; ++p) {
+    const cplx<R>* gr = grid + ((int64_t)cw * g.P + p) * g.L;
+    for (int comp = 0; comp < 2; ++comp) {
+      const int m = g.comp_m[p][comp];
+      if (m == 0) continue;
+      const double pos = ((double)m * v) * (double)g.L + (double)g.c_off;
+      const double fl = floor(pos);
+      const int64_t j0 = (int64_t)fl;
+      const R fr = (R)(pos - fl);
+      R acc = (R)0;
+      for (int dj = -hw - 1; dj <= hw + 1; ++dj) {
+        const R dd = (R)dj - fr;  // (j0 + dj) - pos
+        const R phi = es_kernel<R>(dd * two_over_w, beta);
+        if (phi != (R)0) {
+          const cplx<R> val = gr[j0 + dj];
+          acc += phi * (comp == 0 ? val.x : -val.y);
+        }
+      }
+      if (g.comp_kind[p][comp] == 0) aq += acc;
+      else ap += acc;
+    }
+  }
+  gq[i] = (double)aq;
+  gp[i] = (double)ap;
+}
+
+__global__ __launch_bounds__(kNT) void k_finalize(const double* __restrict__ x,
+                                                  const double* __restrict__ sigma,
+                                                  const Moments* __restrict__ mom, int curve0,
+                                                  const double* __restrict__ dw_part, int bpc,
+                                                  const double* __restrict__ gq,
+                                                  const double* __restrict__ gp,
+                                                  double* __restrict__ grad_x,
+                                                  double* __restrict__ grad_sigma) {
+  __shared__ double red[kNT];
+  const int c = curve0 + blockIdx.x;
+  const int tid = threadIdx.x;
+  const Moments mo = mom[c];
+  const int64_t a = mo.start, b = mo.start + mo.n;
+  if (mo.flags & kCurveFatal) {
+    for (int64_t i = a + tid; i < b; i += kNT) {
+      grad_x[i] = NAN;
+      grad_sigma[i] = NAN;
+    }
+    return;
+  }
+  double s = 0.0;
+  for (int q = tid; q < bpc; q += kNT) s += dw_part[(int64_t)c * bpc + q];
+  red[tid] = s;
+  __syncthreads();
+  for (int st = kNT / 2; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
+    __syncthreads();
+  }
+  const double dW = red[0];
+  __syncthreads();
+  double sg = 0.0;
+  for (int64_t i = a + tid; i < b; i += kNT) {
+    const double si = sigma[i];
+    sg += gp[i] / (si * si);
+  }
+  red[tid] = sg;
+  __syncthreads();
+  for (int st = kNT / 2; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
+    __syncthreads();
+  }
+  const double gbar = red[0] / mo.W;
+  for (int64_t i = a + tid; i < b; i += kNT) {
+    const double si = sigma[i];
+    const double w = 1.0 / (si * si);
+    const double dp = gp[i] - gbar;
+    grad_x[i] = w * dp;
+    const double dLdw = gq[i] + dW + (x[i] - mo.xbar) * dp;
+    grad_sigma[i] = -2.0 * w / si * dLdw;
+  }
+}
+
+template <int H>
+hipError_t adjoint_h(bool fp64, const void* zc, const void* D, const Moments* mom, const Geom& g,
+                     int curve0, int n_curves, double eps, const void* gin, void* spec,
+                     double* dw, int bpc, hipStream_t st) {
+  dim3 gr((unsigned)bpc, (unsigned)n_curves);
+  if (fp64)
+    hipLaunchKernelGGL((k_adjoint<H, double, double>), gr, dim3(kNT), 0, st,
+                       (const cplx<double>*)zc, (const cplx<double>*)D, mom, g, curve0, eps,
+                       (const double*)gin, (cplx<double>*)spec, dw, bpc);
+  else
+    hipLaunchKernelGGL((k_adjoint<H, float, float>), gr, dim3(kNT), 0, st,
+                       (const cplx<float>*)zc, (const cplx<float>*)D, mom, g, curve0, eps,
+                       (const float*)gin, (cplx<float>*)spec, dw, bpc);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_solve(bool fp64, const void* zc, const void* D, const Moments* mom,
+                                const Geom& g, int curve0, int n_curves, double eps_piv,
+                                const void* grad_dchi2, void* spec, double* dW_part,
+                                int blocks_per_curve, hipStream_t st) {
+  switch (g.H) {
+#define FCHI2_ADJ(h) \
+  case h:            \
+    return adjoint_h<h>(fp64, zc, D, mom, g, curve0, n_curves, eps_piv, grad_dchi2, spec, dW_part, blocks_per_curve, st);
+    FCHI2_ADJ(1)
+    FCHI2_ADJ(2)
+    FCHI2_ADJ(3)
+    FCHI2_ADJ(4)
+    FCHI2_ADJ(5)
+    FCHI2_ADJ(6)
+    FCHI2_ADJ(7)
+    FCHI2_ADJ(8)
+#undef FCHI2_ADJ
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gather(bool fp64, const double* t, const Moments* mom, const Geom& g,
+                         int curve0, int n_curves, const void* grid, double* gq, double* gp,
+                         int64_t max_n, hipStream_t st) {
+  dim3 gr((unsigned)((max_n + kNT - 1) / kNT), (unsigned)n_curves);
+  if (gr.x == 0) return hipSuccess;
+  if (fp64)
+    hipLaunchKernelGGL((k_gather<double>), gr, dim3(kNT), 0, st, t, mom, g, curve0,
+                       (const cplx<double>*)grid, gq, gp);
+  else
+    hipLaunchKernelGGL((k_gather<float>), gr, dim3(kNT), 0, st, t, mom, g, curve0,
+                       (const cplx<float>*)grid, gq, gp);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* x, const double* sigma, const Moments* mom,
+                           const Geom& g, int curve0, int n_curves, const double* dW_part,
+                           int blocks_per_curve, const double* gq, const double* gp,
+                           double* grad_x, double* grad_sigma, hipStream_t st) {
+  (void)g;
+  hipLaunchKernelGGL(k_finalize, dim3(n_curves), dim3(kNT), 0, st, x, sigma, mom, curve0,
+                     dW_part, blocks_per_curve, gq, gp, grad_x, grad_sigma);
+  return hipGetLastError();
+}
+
+}  // namespace fchi2

@@ -1,0 +1,69 @@
+// Host-side launchers of the F-chi2 kernels (internal).
+#pragma once
+
+#include "fchi2_internal.h"
+
+namespace fchi2 {
+
+struct FftPassArgs {
+  int kind;                    // PassKind
+  int mode;                    // PassMode
+  int np;                      // number of passes
+  int q;                       // digit handled by this pass (1 = least significant)
+  int logn[kMaxPasses + 1];    // log2 N_d per digit d = 1..np
+  int logL;
+  int tw_s;                    // split of the two-level omega_L table
+  int curve0;                  // first curve of the wave
+  void* zc;                    // forward: pruned spectra [wave][P][2][n_freq]
+  void* grid_out;              // adjoint: natural-order grid output
+};
+
+// Moments, validity flags and chi2_0 of every curve (one workgroup per curve).
+hipError_t launch_moments(const double* t, const double* x, const double* sigma,
+                          const int64_t* offsets, int n_curves, const Geom& g, Moments* mom,
+                          double* chi2_0, hipStream_t st);
+
+// Spread w and w*(x - xbar) of each curve of the wave onto its P packed grids.
+hipError_t launch_spread(bool fp64, const double* t, const double* x, const double* sigma,
+                         const Moments* mom, const Geom& g, int curve0, int n_curves,
+                         void* grid, int log_tile, hipStream_t st);
+
+int fft_tile_log(bool fp64);
+hipError_t launch_fft_pass(bool fp64, const FftPassArgs& a, int logn, int logt, const void* in,
+                           void* out, const Moments* mom, const Geom& g, const void* tws,
+                           const void* twl, const void* twh, int n_curves, int64_t ncols,
+                           hipStream_t st);
+
+// Deconvolution / origin-shift factors D[k] = exp(-2 pi i k c_off / L) / phi_hat(k).
+hipError_t launch_deconv_init(bool fp64, void* D, const Geom& g, const double* gl_x,
+                              const double* gl_w, int n_gl, hipStream_t st);
+
+// Normal-matrix assembly, Cholesky and prefix Delta chi2 per bin.
+hipError_t launch_solve(bool fp64, const void* zc, const void* D, const Moments* mom,
+                        const Geom& g, int curve0, int n_curves, double eps_piv, void* dchi2,
+                        uint8_t* flags, hipStream_t st);
+
+// Adjoint of the solve: per-bin gradients into the packed adjoint spectra.
+hipError_t launch_adjoint_solve(bool fp64, const void* zc, const void* D, const Moments* mom,
+                                const Geom& g, int curve0, int n_curves, double eps_piv,
+                                const void* grad_dchi2, void* spec, double* dW_part,
+                                int blocks_per_curve, hipStream_t st);
+
+// Interpolate the adjoint grids at the points (transpose of the spreading).
+hipError_t launch_gather(bool fp64, const double* t, const Moments* mom, const Geom& g,
+                         int curve0, int n_curves, const void* grid, double* gq, double* gp,
+                         int64_t max_n, hipStream_t st);
+
+// Reduce the per-curve terms and write d/dx, d/dsigma.
+hipError_t launch_finalize(const double* x, const double* sigma, const Moments* mom,
+                           const Geom& g, int curve0, int n_curves, const double* dW_part,
+                           int blocks_per_curve, const double* gq, const double* gp,
+                           double* grad_x, double* grad_sigma, hipStream_t st);
+
+// Top-K strict local maxima of one Delta chi2 row per curve.
+hipError_t launch_peaks(bool fp64, const void* dchi2, int64_t n_freq, int H, int hrow,
+                        int n_curves, int64_t k_lo, int K, void* scratch, int64_t* out_idx,
+                        hipStream_t st);
+size_t peaks_scratch_bytes(int64_t n_freq, int n_curves, int K);
+
+}  // namespace fchi2

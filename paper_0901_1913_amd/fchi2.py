@@ -1,0 +1,307 @@
+"""Python binding of the F-chi2 C ABI (include/fchi2.h).
+
+Argument marshalling only: every step of the search and of its adjoint runs in
+the HIP kernels of libfchi2.so.  PyTorch supplies device memory and the
+current stream.  The library must be built (``python -m
+paper_0901_1913_amd.build``); nothing here falls back to another
+implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfchi2.so")
+
+OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = range(6)
+FP64, MIXED = 0, 1
+KEEP_FOR_BACKWARD, GRAPH = 1, 2
+H_MAX = 8
+BIN_PIVOT, BIN_LOW_F, BIN_DC = 1, 2, 4
+CURVE_NONFINITE, CURVE_UNSORTED, CURVE_WRAP, CURVE_FEW, CURVE_EMPTY = 8, 16, 32, 64, 128
+
+EXPORTS = (
+    "fchi2_plan", "fchi2_workspace_bytes", "fchi2_total_points", "fchi2_search",
+    "fchi2_backward", "fchi2_top_peaks_scratch_bytes", "fchi2_top_peaks",
+    "fchi2_destroy", "fchi2_status_string", "fchi2_last_error",
+)
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_curves", ctypes.c_int32),
+        ("offsets", ctypes.POINTER(ctypes.c_int64)),
+        ("f_max", ctypes.c_double),
+        ("H", ctypes.c_int32),
+        ("n_freq", ctypes.c_int64),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("kernel_width", ctypes.c_int32),
+        ("curves_per_wave", ctypes.c_int32),
+    ]
+
+
+class FChi2Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fchi2 status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfchi2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_0901_1913_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64
+    L.fchi2_plan.argtypes = [ctypes.POINTER(PlanDesc), vp, ctypes.POINTER(vp)]
+    L.fchi2_plan.restype = ctypes.c_int
+    L.fchi2_workspace_bytes.argtypes = [vp]
+    L.fchi2_workspace_bytes.restype = sz
+    L.fchi2_total_points.argtypes = [vp]
+    L.fchi2_total_points.restype = i64
+    L.fchi2_search.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp, vp]
+    L.fchi2_search.restype = ctypes.c_int
+    L.fchi2_backward.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
+    L.fchi2_backward.restype = ctypes.c_int
+    L.fchi2_top_peaks_scratch_bytes.argtypes = [vp, i32]
+    L.fchi2_top_peaks_scratch_bytes.restype = sz
+    L.fchi2_top_peaks.argtypes = [vp, vp, i32, i64, i32, vp, sz, vp, vp]
+    L.fchi2_top_peaks.restype = ctypes.c_int
+    L.fchi2_destroy.argtypes = [vp]
+    L.fchi2_destroy.restype = None
+    L.fchi2_status_string.argtypes = [ctypes.c_int]
+    L.fchi2_status_string.restype = ctypes.c_char_p
+    L.fchi2_last_error.argtypes = []
+    L.fchi2_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != OK:
+        msg = lib().fchi2_last_error().decode() or lib().fchi2_status_string(status).decode()
+        raise FChi2Error(status, msg)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev_ptr(tensor, dtype, n=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(tensor, torch.Tensor) or not tensor.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if tensor.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {tensor.dtype}")
+    if not tensor.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and tensor.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {tensor.numel()}")
+    return ctypes.c_void_p(tensor.data_ptr())
+
+
+class Plan:
+    """A search plan: geometry, FFT split and device tables for a set of curves."""
+
+    def __init__(self, offsets: Sequence[int], f_max: float, H: int, n_freq: int,
+                 precision: str = "mixed", keep_for_backward: bool = False,
+                 graph: bool = False, kernel_width: int = 0, curves_per_wave: int = 0,
+                 stream=None):
+        torch = _torch()
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        if off.ndim != 1 or off.shape[0] < 2:
+            raise ValueError("offsets must be a 1-D array of n_curves + 1 entries")
+        if precision not in ("mixed", "fp64"):
+            raise ValueError("precision must be 'mixed' or 'fp64'")
+        self._off = off
+        flags = (KEEP_FOR_BACKWARD if keep_for_backward else 0) | (GRAPH if graph else 0)
+        desc = PlanDesc(
+            n_curves=off.shape[0] - 1,
+            offsets=off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            f_max=float(f_max), H=int(H), n_freq=int(n_freq),
+            precision=FP64 if precision == "fp64" else MIXED,
+            flags=flags, kernel_width=int(kernel_width),
+            curves_per_wave=int(curves_per_wave))
+        handle = ctypes.c_void_p()
+        st = _stream_handle(stream) if torch.cuda.is_available() else 0
+        _check(lib().fchi2_plan(ctypes.byref(desc), ctypes.c_void_p(st), ctypes.byref(handle)))
+        self._h = handle
+        self.n_curves = off.shape[0] - 1
+        self.n_total = int(off[-1])
+        self.H, self.n_freq, self.f_max = int(H), int(n_freq), float(f_max)
+        self.precision = precision
+        self.keep_for_backward = keep_for_backward
+        self.out_dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.workspace_bytes = int(lib().fchi2_workspace_bytes(self._h))
+        self._ws = None
+
+    # -- memory -----------------------------------------------------------
+    def workspace(self, device="cuda"):
+        """Allocate (once) and return the plan's workspace tensor."""
+        torch = _torch()
+        if self._ws is None:
+            # torch allocations are 512-byte aligned on ROCm.
+            self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8,
+                                   device=device)
+        return self._ws
+
+    @property
+    def freqs(self) -> np.ndarray:
+        return np.arange(self.n_freq, dtype=np.float64) * (self.f_max / self.n_freq)
+
+    # -- entry points ---------------------------------------------------------
+    def search(self, t, x, sigma, dchi2=None, chi2_0=None, flags=None, workspace=None,
+               stream=None, want_flags=True):
+        """Delta chi2 [n_curves, H, n_freq], chi2_0 [n_curves], flags [n_curves, n_freq]."""
+        torch = _torch()
+        f64 = torch.float64
+        pt = _dev_ptr(t, f64, self.n_total, "t")
+        px = _dev_ptr(x, f64, self.n_total, "x")
+        ps = _dev_ptr(sigma, f64, self.n_total, "sigma")
+        dev = t.device
+        if dchi2 is None:
+            dchi2 = torch.empty((self.n_curves, self.H, self.n_freq), dtype=self.out_dtype,
+                                device=dev)
+        if chi2_0 is None:
+            chi2_0 = torch.empty(self.n_curves, dtype=f64, device=dev)
+        if flags is None and want_flags:
+            flags = torch.empty((self.n_curves, self.n_freq), dtype=torch.uint8, device=dev)
+        ws = self.workspace(dev) if workspace is None else workspace
+        _check(lib().fchi2_search(
+            self._h, pt, px, ps, ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+            _dev_ptr(dchi2, self.out_dtype, self.n_curves * self.H * self.n_freq, "dchi2"),
+            _dev_ptr(chi2_0, f64, self.n_curves, "chi2_0"),
+            _dev_ptr(flags, torch.uint8, self.n_curves * self.n_freq, "flags")
+            if flags is not None else ctypes.c_void_p(0),
+            ctypes.c_void_p(_stream_handle(stream))))
+        return dchi2, chi2_0, flags
+
+    def backward(self, t, x, sigma, grad_dchi2, grad_x=None, grad_sigma=None,
+                 workspace=None, stream=None):
+        """dLoss/dx and dLoss/dsigma given dLoss/dDelta chi2 (same layout as dchi2)."""
+        torch = _torch()
+        f64 = torch.float64
+        dev = t.device
+        if grad_x is None:
+            grad_x = torch.empty(self.n_total, dtype=f64, device=dev)
+        if grad_sigma is None:
+            grad_sigma = torch.empty(self.n_total, dtype=f64, device=dev)
+        ws = self.workspace(dev) if workspace is None else workspace
+        _check(lib().fchi2_backward(
+            self._h, _dev_ptr(t, f64, self.n_total, "t"), _dev_ptr(x, f64, self.n_total, "x"),
+            _dev_ptr(sigma, f64, self.n_total, "sigma"),
+            _dev_ptr(grad_dchi2, self.out_dtype, self.n_curves * self.H * self.n_freq,
+                     "grad_dchi2"),
+            ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+            _dev_ptr(grad_x, f64, self.n_total, "grad_x"),
+            _dev_ptr(grad_sigma, f64, self.n_total, "grad_sigma"),
+            ctypes.c_void_p(_stream_handle(stream))))
+        return grad_x, grad_sigma
+
+    def top_peaks(self, dchi2, hrow: int, k_lo: int, K: int, out=None, stream=None):
+        """[n_curves, K] int64 bins of the K largest strict local maxima (-1 if fewer)."""
+        torch = _torch()
+        nbytes = int(lib().fchi2_top_peaks_scratch_bytes(self._h, int(K)))
+        scratch = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dchi2.device)
+        if out is None:
+            out = torch.empty((self.n_curves, K), dtype=torch.int64, device=dchi2.device)
+        _check(lib().fchi2_top_peaks(
+            self._h, _dev_ptr(dchi2, self.out_dtype, None, "dchi2"), int(hrow), int(k_lo),
+            int(K), ctypes.c_void_p(scratch.data_ptr()), ctypes.c_size_t(scratch.numel()),
+            _dev_ptr(out, torch.int64, self.n_curves * K, "out"),
+            ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fchi2_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def search(t, x, sigma, f_max: float, H: int, n_freq: int, precision: str = "mixed",
+           offsets=None, **plan_kw):
+    """One-shot search over device tensors; returns (dchi2, chi2_0, flags)."""
+    if offsets is None:
+        offsets = [0, int(t.numel())]
+    plan = Plan(offsets, f_max, H, n_freq, precision=precision, **plan_kw)
+    try:
+        return plan.search(t, x, sigma)
+    finally:
+        import torch
+        torch.cuda.current_stream().synchronize()
+        plan.close()
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class FChi2Fn(torch.autograd.Function):
+        """Delta chi2 with the hand-written adjoint as its backward.
+
+        forward(t, x, sigma, plan) -> dchi2 [n_curves, H, n_freq]; the plan
+        must have keep_for_backward=True.  backward returns gradients for x
+        and sigma (t is not differentiated).
+        """
+
+        @staticmethod
+        def forward(ctx, t, x, sigma, plan):
+            if not plan.keep_for_backward:
+                raise ValueError("FChi2Fn needs a plan with keep_for_backward=True")
+            dchi2, _, _ = plan.search(t, x, sigma, want_flags=False)
+            ctx.plan = plan
+            ctx.save_for_backward(t, x, sigma)
+            return dchi2
+
+        @staticmethod
+        def backward(ctx, grad):
+            t, x, sigma = ctx.saved_tensors
+            plan = ctx.plan
+            g = grad.to(plan.out_dtype).contiguous()
+            gx, gs = plan.backward(t, x, sigma, g)
+            return None, gx, gs, None
+
+    return FChi2Fn
+
+
+class _Lazy:
+    _fn = None
+
+    def __get__(self, obj, objtype=None):
+        if _Lazy._fn is None:
+            _Lazy._fn = _make_autograd()
+        return _Lazy._fn
+
+
+class _Holder:
+    FChi2Fn = _Lazy()
+
+
+def fchi2_fn():
+    """The torch.autograd.Function wrapping search/backward."""
+    return _Holder.FChi2Fn

@@ -1,0 +1,38 @@
+"""Helpers for the GPU tests: run the HIP path through the C ABI binding."""
+import sys
+
+import numpy as np
+
+from paper_0901_1913_amd import fchi2 as F
+
+
+def note(msg):
+    """Name the case before a GPU step (flushed so a crash still shows it)."""
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(curves):
+    import torch
+    t = torch.from_numpy(curves.t).cuda()
+    x = torch.from_numpy(curves.x).cuda()
+    s = torch.from_numpy(curves.sigma).cuda()
+    return t, x, s
+
+
+def run_search(curves, precision=None, **plan_kw):
+    """Delta chi2 [n_curves, H, n_freq] (float64 numpy), chi2_0, flags, plan."""
+    import torch
+    precision = precision or curves.precision
+    plan = F.Plan(curves.offsets, curves.f_max, curves.H, curves.n_freq,
+                  precision=precision, **plan_kw)
+    t, x, s = to_dev(curves)
+    d, c0, fl = plan.search(t, x, s)
+    torch.cuda.synchronize()
+    return (d.double().cpu().numpy(), c0.cpu().numpy(), fl.cpu().numpy(), plan)
+
+
+def sample_bins(n_freq, n, seed, k_min=1):
+    rng = np.random.default_rng(seed)
+    b = rng.choice(np.arange(k_min, n_freq), size=min(n, n_freq - k_min), replace=False)
+    return np.sort(np.concatenate([b, [k_min, n_freq - 1]])).astype(np.int64)

@@ -1,0 +1,183 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerance (from the target): relative error on Delta chi2 <= 1e-5, measured as
+|d_gpu - d_ora| / max(d_ora, 2H') on gated bins: k >= 1, f_k >= 1/span and a
+scaled condition number kappa <= 1e2 (mixed) or 1e6 (FP64) of the normal
+matrix.  The FP64 path is also held to 1e-8 (its kernel width makes the
+gridding error ~1e-11).
+"""
+import numpy as np
+import pytest
+
+from oracle import fchi2_oracle as ora
+from paper_0901_1913_amd import fchi2 as F
+from paper_0901_1913_amd import synth
+from tests.gpu_util import note, run_search, sample_bins, to_dev
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = {"mixed": 1e2, "fp64": 1e6}
+
+
+def _check(curves, d_gpu, bins, precision, tol, c=0, label=""):
+    t, x, s = curves.curve(c)
+    freqs = bins * (curves.f_max / curves.n_freq)
+    res = ora.dchi2(t, x, s, freqs, curves.H)
+    err = ora.rel_err(d_gpu[c][:, bins], res["dchi2"])
+    gate = ora.gate_mask(res, freqs, KAPPA[precision])
+    assert gate.sum() > 0.5 * len(bins), "gate removed most bins"
+    e = err[:, gate]
+    print(f"{label}: gated bins {gate.sum()}/{len(bins)} max {e.max():.3e} "
+          f"median {np.median(e):.3e}; ungated max {err.max():.3e}", flush=True)
+    assert e.max() <= tol, (label, e.max())
+    return res
+
+
+def test_plain_fp64_every_bin():
+    cur = synth.make("plain", n_freq=2 ** 12, f_max=2.5)
+    note("plain fp64 n_freq=2^12 all bins")
+    d, c0, fl, _ = run_search(cur, "fp64")
+    bins = np.arange(1, cur.n_freq)
+    res = _check(cur, d, bins, "fp64", 1e-8, label="plain fp64 2^12")
+    np.testing.assert_allclose(c0[0], res["chi2_0"], rtol=1e-12)
+    assert d[0][:, 0].tolist() == [0.0] * cur.H and fl[0, 0] & F.BIN_DC
+
+
+def test_plain_fp64_full_size_sampled():
+    cur = synth.make("plain")
+    note("plain fp64 n_freq=2^14 sampled")
+    d, _, _, _ = run_search(cur, "fp64")
+    k0 = int(round(cur.n_freq / cur.f_max / 2.37))
+    bins = np.unique(np.concatenate([sample_bins(cur.n_freq, 600, 11),
+                                     np.arange(k0 - 8, k0 + 9)]))
+    _check(cur, d, bins, "fp64", 1e-8, label="plain fp64 2^14")
+    # The best bin is the injected period.
+    assert abs(int(np.argmax(d[0][2])) - k0) <= 1
+
+
+def _long_small():
+    return synth.make("long", n=5000, span=300.0, n_freq=2 ** 14, f_max=5.0)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_long_small_sampled(precision):
+    cur = _long_small()
+    note(f"long-small {precision}")
+    d, _, _, _ = run_search(cur, precision)
+    k0 = int(round(cur.n_freq / cur.f_max / 0.731))
+    bins = np.unique(np.concatenate([sample_bins(cur.n_freq, 500, 12),
+                                     np.arange(k0 - 4, k0 + 5),
+                                     2 * k0 + np.arange(-3, 4)]))
+    _check(cur, d, bins, precision, 1e-5 if precision == "mixed" else 1e-8,
+           label=f"long-small {precision}")
+
+
+def test_mixed_against_fp64_gpu_every_bin():
+    cur = _long_small()
+    note("long-small mixed vs fp64 gpu")
+    dm, _, flm, _ = run_search(cur, "mixed")
+    dd, _, _, _ = run_search(cur, "fp64")
+    floor = (2.0 * np.arange(1, cur.H + 1))[:, None]
+    err = np.abs(dm[0] - dd[0]) / np.maximum(dd[0], floor)
+    k = np.arange(cur.n_freq)
+    span = cur.t.max() - cur.t.min()
+    ok = (k >= 1) & (k * cur.f_max / cur.n_freq >= 1.0 / span) & ((flm[0] & F.BIN_PIVOT) == 0)
+    print(f"mixed vs fp64: max {err[:, ok].max():.3e} median {np.median(err[:, ok]):.3e}")
+    assert np.percentile(err[:, ok], 99.9) <= 1e-5
+
+
+def test_min_size_single_pass_fft():
+    for prec in ("mixed", "fp64"):
+        cur = synth.make("plain", n=200, n_freq=2 ** 10, f_max=0.6, precision=prec)
+        note(f"n_freq=2^10 {prec}")
+        d, _, _, _ = run_search(cur, prec)
+        _check(cur, d, np.arange(1, cur.n_freq), prec, 1e-5 if prec == "mixed" else 1e-8,
+               label=f"min size {prec}")
+
+
+def _batch_with_bad_curves():
+    b = synth.batch(n_curves=10, n_lo=20, n_hi=400, span_lo=30.0, span_hi=100.0,
+                    n_freq=2 ** 12, f_max=6.0)
+    rng = np.random.default_rng(5)
+    ts, xs, ss = [b.t], [b.x], [b.sigma]
+    lens = list(np.diff(b.offsets))
+    extra = []
+    # few points (valid, pivots dropped), unsorted, NaN x, sigma = 0, empty
+    t = np.sort(rng.uniform(0, 50, 3)); extra.append((t, rng.standard_normal(3), np.full(3, 0.1)))
+    t = rng.uniform(0, 50, 50)  # not sorted
+    extra.append((t, rng.standard_normal(50), np.full(50, 0.1)))
+    t = np.sort(rng.uniform(0, 50, 50)); xx = rng.standard_normal(50); xx[9] = np.nan
+    extra.append((t, xx, np.full(50, 0.1)))
+    t = np.sort(rng.uniform(0, 50, 50)); sg = np.full(50, 0.1); sg[4] = 0.0
+    extra.append((t, rng.standard_normal(50), sg))
+    extra.append((np.zeros(0), np.zeros(0), np.zeros(0)))
+    for t, xx, sg in extra:
+        ts.append(t); xs.append(xx); ss.append(sg); lens.append(len(t))
+    off = np.zeros(len(lens) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    return synth.Curves(t=np.concatenate(ts), x=np.concatenate(xs),
+                        sigma=np.concatenate(ss), offsets=off, H=b.H, n_freq=b.n_freq,
+                        f_max=b.f_max, precision="mixed", name="batch+bad")
+
+
+def test_batch_uneven_lengths_and_isolation():
+    cur = _batch_with_bad_curves()
+    note("batch with bad curves, waves of 4")
+    d, c0, fl, _ = run_search(cur, "mixed", curves_per_wave=4)
+    nb = cur.n_curves
+    good = list(range(10))
+    # rejected curves: NaN outputs and their curve bits
+    for c, bit in [(11, F.CURVE_UNSORTED), (12, F.CURVE_NONFINITE),
+                   (13, F.CURVE_NONFINITE), (14, F.CURVE_EMPTY)]:
+        assert np.all(np.isnan(d[c])), c
+        assert np.all(fl[c] & bit), (c, fl[c][:4])
+        assert np.isnan(c0[c])
+    # the few-point curve is valid; its pivots are dropped
+    assert np.all(np.isfinite(d[10])) and np.any(fl[10] & F.BIN_PIVOT)
+    # every good curve equals its own single-curve run, bit for bit
+    for c in good:
+        a, b = int(cur.offsets[c]), int(cur.offsets[c + 1])
+        one = synth.Curves(t=cur.t[a:b], x=cur.x[a:b], sigma=cur.sigma[a:b],
+                           offsets=np.array([0, b - a]), H=cur.H, n_freq=cur.n_freq,
+                           f_max=cur.f_max, precision="mixed")
+        note(f"batch curve {c} alone")
+        d1, _, _, _ = run_search(one, "mixed")
+        assert np.array_equal(d1[0], d[c]), c
+    for c in (0, 3, 9):
+        _check(cur, d, sample_bins(cur.n_freq, 200, 20 + c), "mixed", 1e-5, c=c,
+               label=f"batch curve {c}")
+
+
+def test_deterministic_and_graph_replay():
+    import torch
+    cur = _long_small()
+    note("determinism + graph replay")
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed")
+    t, x, s = to_dev(cur)
+    d1, _, f1 = plan.search(t, x, s)
+    d1 = d1.clone()
+    d2, _, f2 = plan.search(t, x, s)
+    torch.cuda.synchronize()
+    assert torch.equal(d1, d2) and torch.equal(f1, f2)
+    gplan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed", graph=True)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        out = torch.empty_like(d1)
+        c0 = torch.empty(1, dtype=torch.float64, device="cuda")
+        fl = torch.empty_like(f1)
+        for rep in range(3):
+            out.zero_()
+            gplan.search(t, x, s, dchi2=out, chi2_0=c0, flags=fl)
+            st.synchronize()
+            assert torch.equal(out, d1), rep
+    torch.cuda.synchronize()
+
+
+def test_constant_data_gives_zero():
+    cur = synth.make("plain", n=300, n_freq=2 ** 12, f_max=2.5)
+    cur.x[:] = 1.25
+    note("constant data")
+    d, c0, _, _ = run_search(cur, "fp64")
+    assert abs(c0[0]) < 1e-20
+    assert np.max(np.abs(d)) < 1e-12
