@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Throughput of the F-chi2 hot path on one MI355X.
+
+A step is one fchi2_search over the whole workload (moments, spreading, FFT
+passes, per-bin assembly and Cholesky for every H'), with the inputs already
+resident in device memory.  The value is trial frequencies x H per second.
+
+Prints one JSON line.  Beside the throughput it reports, for the kernel that
+takes the most time, its algorithmic bytes per launch divided by its average
+launch time (HIP events recorded by the library on the search stream during
+the timed steps), and the FP64 CPU oracle timed on a bounded sample of bins of
+the same workload (whose values double as a parity spot check).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("trial freqs·H/sec for Δχ² (rel err ≤1e-5 vs FP64 oracle); "
+          "batched vs plain")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pair_extents(cur, w):
+    """Nonzero cells of each packed grid (weight pairs, then data pairs)."""
+    H, nf = cur.H, cur.n_freq
+    L = 4 * nf
+    df = cur.f_max / nf
+    span = float(cur.t[-1] - cur.t[0])
+    c_off = w // 2 + 2
+    ms = [2 * p + 2 for p in range(H)] + [min(2 * j + 2, H) for j in range((H + 1) // 2)]
+    return [min(L, int((m * (span * df)) * L + c_off) + w // 2 + 1) for m in ms]
+
+
+def stage_bytes(cur, elem, out_elem, w):
+    """Algorithmic HBM bytes per launch of each forward stage (one curve)."""
+    H, nf = cur.H, cur.n_freq
+    L = 4 * nf
+    P = H + (H + 1) // 2
+    E = pair_extents(cur, w)
+    n = cur.t.shape[0]
+    return {
+        "moments": 24 * n,
+        "spread": 24 * n + sum(E) * elem,
+        "fft_first": sum(E) * elem + P * L * elem,
+        "fft_mid": 2 * P * L * elem,
+        "fft_last": P * L * elem + P * 2 * nf * elem,
+        "solve": P * 2 * nf * elem + nf * elem + H * nf * out_elem + nf,
+    }
+
+
+def _oracle_chunk(args):
+    t, x, s, freqs, H = args
+    from threadpoolctl import threadpool_limits
+    from oracle import fchi2_oracle as ora
+    with threadpool_limits(1):
+        r = ora.dchi2(t, x, s, freqs, H)
+    return r["dchi2"], r["kappa"]
+
+
+def cpu_baseline(cur, budget_s, seed=7):
+    """Time the oracle on a seeded bin sample sized to ~budget_s of CPU work."""
+    import multiprocessing as mp
+    cores = max(1, min(16, os.cpu_count() or 1))
+    t, x, s = cur.curve(0)
+    rng = np.random.default_rng(seed)
+    nf = cur.n_freq
+    # Probe the cost of one bin on one core.
+    probe = np.array([nf // 3], dtype=np.int64)
+    t0 = time.perf_counter()
+    _oracle_chunk((t, x, s, probe * (cur.f_max / nf), cur.H))
+    per_bin = max(time.perf_counter() - t0, 1e-4)
+    n_bins = int(max(cores, min(4096, budget_s * cores / per_bin)))
+    n_bins = (n_bins // cores) * cores
+    bins = np.sort(rng.choice(np.arange(1, nf), size=n_bins, replace=False))
+    chunks = np.array_split(bins, cores)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        parts = pool.map(_oracle_chunk, [(t, x, s, c * (cur.f_max / nf), cur.H) for c in chunks])
+    el = time.perf_counter() - t0
+    return (bins, np.concatenate([p[0] for p in parts], axis=1),
+            np.concatenate([p[1] for p in parts]), el, cores)
+
+
+def batched_vs_plain(steps):
+    """The batch workload as one graph-replayed search vs a loop of single-curve searches."""
+    import torch
+    from paper_0901_1913_amd import fchi2 as F
+    from paper_0901_1913_amd import synth
+    cur = synth.make("batch")
+    log(f"batch: {cur.n_curves} curves, {cur.t.shape[0]} points, H={cur.H}, "
+        f"n_freq={cur.n_freq}")
+    t = torch.from_numpy(cur.t).cuda()
+    x = torch.from_numpy(cur.x).cuda()
+    s = torch.from_numpy(cur.sigma).cuda()
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision,
+                  graph=True)
+    ws = plan.workspace()
+    dchi2 = torch.empty((cur.n_curves, cur.H, cur.n_freq), dtype=plan.out_dtype, device="cuda")
+    chi2_0 = torch.empty(cur.n_curves, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    units = cur.n_curves * cur.n_freq * cur.H
+    with torch.cuda.stream(stream):
+        plan.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, workspace=ws, want_flags=False)
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            plan.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, workspace=ws, want_flags=False)
+        e1.record(stream)
+        stream.synchronize()
+        ms_b = e0.elapsed_time(e1) / steps
+        ref = dchi2.clone()
+        log(f"batched: {ms_b:.3f} ms/step")
+        # Plain form: the same kernels, one curve per call, no graph.
+        e0.record(stream)
+        for c in range(cur.n_curves):
+            plan.search_curves(c, 1, t, x, s, dchi2, chi2_0, workspace=ws, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+        ms_p = e0.elapsed_time(e1)
+        same = bool(torch.equal(ref, dchi2))
+        log(f"plain loop: {ms_p:.3f} ms per pass (results identical: {same})")
+    plan.close()
+    torch.cuda.synchronize()
+    return {"workload": "batch", "n_curves": cur.n_curves, "n_total": int(cur.t.shape[0]),
+            "H": cur.H, "n_freq": cur.n_freq, "precision": cur.precision,
+            "batched_value": round(units / (ms_b * 1e-3), 1), "batched_ms_per_step": round(ms_b, 4),
+            "plain_value": round(units / (ms_p * 1e-3), 1), "plain_ms_per_pass": round(ms_p, 3),
+            "speedup": round(ms_p / ms_b, 3), "identical_outputs": same,
+            "unit": "freq*H/s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="long",
+                    choices=["plain", "long", "diff", "stress"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-survey vs plain-loop comparison")
+    ap.add_argument("--batched-steps", type=int, default=5)
+    a = ap.parse_args(argv)
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for {max(a.gpus, world)}); the search "
+              "shards by curves or frequency bands across GPUs, which this build does not "
+              "run.", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_0901_1913_amd import fchi2 as F
+    from paper_0901_1913_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    cur = synth.make(a.workload)
+    log(f"workload {a.workload}: n={cur.t.shape[0]} H={cur.H} n_freq={cur.n_freq} "
+        f"precision={cur.precision}")
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision)
+    t = torch.from_numpy(cur.t).cuda()
+    x = torch.from_numpy(cur.x).cuda()
+    s = torch.from_numpy(cur.sigma).cuda()
+    ws = plan.workspace()
+    dchi2 = torch.empty((1, cur.H, cur.n_freq), dtype=plan.out_dtype, device="cuda")
+    chi2_0 = torch.empty(1, dtype=torch.float64, device="cuda")
+    flags = torch.empty((1, cur.n_freq), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(a.warmup):
+        plan.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, flags=flags, workspace=ws)
+    torch.cuda.synchronize()
+    log(f"warmup done ({a.warmup})")
+
+    plan.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(a.steps):
+        plan.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, flags=flags, workspace=ws)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_step = ev0.elapsed_time(ev1) / a.steps
+    stages = plan.profile_read()
+    plan.profile(False)
+    log(f"timed {a.steps} steps: {ms_step:.4f} ms/step (wall {1e3 * wall / a.steps:.4f})")
+
+    units = cur.n_curves * cur.n_freq * cur.H
+    value = units / (ms_step * 1e-3)
+    w = plan.info()["kernel_width"]
+    elem = 8 if cur.precision == "mixed" else 16
+    out_elem = 4 if cur.precision == "mixed" else 8
+    nbytes = stage_bytes(cur, elem, out_elem, w)
+    st_avg = {k: (v[0] / v[1] if v[1] else 0.0, v[1] // a.steps) for k, v in stages.items()
+              if v[1]}
+    per_step = {k: round(v[0] * v[1], 5) for k, v in st_avg.items()}
+    dom = max(per_step, key=per_step.get)
+    dom_ms = st_avg[dom][0]
+    achieved = nbytes[dom] / (dom_ms * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "bytes_per_launch": int(nbytes[dom]),
+            "avg_launch_ms": round(dom_ms, 5)}
+    stage_gbs = {k: round(nbytes[k] / (v[0] * 1e-3) / 1e9, 1) for k, v in st_avg.items()
+                 if k in nbytes and v[0] > 0}
+
+    d_gpu = dchi2.double().cpu().numpy()[0]
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "freq*H/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if cur.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": a.workload, "n": int(cur.t.shape[0]), "H": cur.H,
+                   "n_freq": cur.n_freq, "f_max": cur.f_max, "precision": cur.precision,
+                   "schedule": plan.info()},
+        "roofline": roof,
+        "stages_ms_per_step": per_step,
+        "stages_gbs": stage_gbs,
+    }
+    if not a.no_cpu_baseline:
+        from oracle import fchi2_oracle as ora
+        log("oracle CPU baseline ...")
+        bins, d_ora, kappa, el, cores = cpu_baseline(cur, a.cpu_seconds)
+        out["cpu_baseline"] = {
+            "value": round(len(bins) * cur.H / el, 2), "unit": "freq*H/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{len(bins)} seeded random bins of the {a.workload} workload "
+                      f"(all H'=1..{cur.H}), {el:.1f} s wall"}
+        span = float(cur.t[-1] - cur.t[0])
+        freqs = bins * (cur.f_max / cur.n_freq)
+        err = ora.rel_err(d_gpu[:, bins], d_ora)
+        kmax = 1e2 if cur.precision == "mixed" else 1e6
+        ok = (freqs >= 1.0 / span) & (kappa <= kmax)
+        out["parity"] = {"bins": int(len(bins)), "gated_bins": int(ok.sum()),
+                         "gate": f"f >= 1/span, kappa <= {kmax:g}",
+                         "max_rel_err_gated": float(err[:, ok].max()) if ok.any() else None,
+                         "median_rel_err_gated": float(np.median(err[:, ok])) if ok.any() else None,
+                         "max_rel_err_all": float(err.max())}
+    plan.close()
+    del dchi2, ws
+    if not a.no_batched:
+        out["batched"] = batched_vs_plain(a.batched_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -135,6 +135,19 @@ fchi2_status_t fchi2_search(fchi2_plan_t plan, const double* t, const double* x,
                             void* dchi2, double* chi2_0, uint8_t* flags, void* stream);
 
 /*
+ * fchi2_search restricted to curves [first, first + count) of the plan: the
+ * same kernels over fewer curves (count = 1 is the plain single-curve form).
+ * Arguments and layouts are those of fchi2_search (full-size arrays; only the
+ * rows of the selected curves are written).  Never replayed through a graph.
+ * A search over a strict subset leaves no state for fchi2_backward.
+ * Errors: as fchi2_search, and FCHI2_ERR_ARG for a range outside the plan.
+ */
+fchi2_status_t fchi2_search_curves(fchi2_plan_t plan, int32_t first, int32_t count,
+                                   const double* t, const double* x, const double* sigma,
+                                   void* workspace, size_t workspace_bytes, void* dchi2,
+                                   double* chi2_0, uint8_t* flags, void* stream);
+
+/*
  * Gradient of a scalar loss through Delta chi2 (adjoint of the whole chain:
  * solve, assembly, deconvolution, FFT and spreading, then the weighted mean;
  * derived from eq. eqchigen and eq. eqchix).
@@ -165,6 +178,55 @@ size_t fchi2_top_peaks_scratch_bytes(fchi2_plan_t plan, int32_t K);
 fchi2_status_t fchi2_top_peaks(fchi2_plan_t plan, const void* dchi2, int32_t hrow, int64_t k_lo,
                                int32_t K, void* scratch, size_t scratch_bytes, int64_t* out_idx,
                                void* stream);
+
+/*
+ * Measurement support.  fchi2_profile(plan, 1) makes every later
+ * fchi2_search / fchi2_backward on the plan record a HIP event pair around
+ * each kernel launch, on the stream of that call (graph replay is bypassed
+ * while profiling).  fchi2_profile_read waits for the recorded events and
+ * fills total_ms[s] (milliseconds summed over launches) and launches[s] for
+ * each stage s = FCHI2_PROF_*, accumulated since fchi2_profile was last
+ * called.  fchi2_profile(plan, 0) stops recording and clears the totals.
+ *  total_ms, launches  host arrays of FCHI2_PROF_STAGES entries
+ * Errors: FCHI2_ERR_ARG (NULL), FCHI2_ERR_HIP.
+ */
+#define FCHI2_PROF_MOMENTS 0
+#define FCHI2_PROF_SPREAD 1
+#define FCHI2_PROF_FFT_FIRST 2
+#define FCHI2_PROF_FFT_MID 3
+#define FCHI2_PROF_FFT_LAST 4
+#define FCHI2_PROF_SOLVE 5
+#define FCHI2_PROF_BWD_SOLVE 6
+#define FCHI2_PROF_BWD_FFT 7
+#define FCHI2_PROF_BWD_GATHER 8
+#define FCHI2_PROF_BWD_FINAL 9
+#define FCHI2_PROF_STAGES 10
+fchi2_status_t fchi2_profile(fchi2_plan_t plan, int32_t enable);
+fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* launches);
+
+/*
+ * Autotuner.  Times every candidate schedule of the plan on the caller's data
+ * (the FFT digit splits with the fewest passes, spreading tiles of 1024 or
+ * 2048 cells, and waves of wave_max, wave_max/2, wave_max/4 curves) with HIP
+ * events on `stream`, keeps the fastest in the plan, and appends it to the
+ * text file `cache_path` (may be NULL) keyed by the shape bucket (H, n_freq,
+ * precision, kernel width, log2 curves, log2 largest curve, wave_max).  If
+ * the file already holds the key, the cached schedule is applied without
+ * timing.  The outputs of later searches may differ from the untuned plan's
+ * only by rounding.  Synchronises `stream`; not for graph capture.
+ *  t, x, sigma, workspace, dchi2  as for fchi2_search (dchi2 is scratch here)
+ * Errors: FCHI2_ERR_ARG, FCHI2_ERR_HIP.
+ */
+fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* x,
+                              const double* sigma, void* workspace, size_t workspace_bytes,
+                              void* dchi2, const char* cache_path, void* stream);
+
+/*
+ * Current schedule of a plan: info[0] = FFT passes, info[1..4] = log2 radix of
+ * digits 1..4 (0 if unused), info[5] = log2 spreading tile, info[6] = curves
+ * per wave, info[7] = kernel width.  n must be >= 8.
+ */
+fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n);
 
 /* Free the plan and its device tables (no-op for NULL). */
 void fchi2_destroy(fchi2_plan_t plan);

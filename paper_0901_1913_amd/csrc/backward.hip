@@ -91,7 +91,7 @@ __device__ __forceinline__ void alpha_adj(int i, int j, double v, double* dQr, d
 
 template <int H, typename R, typename O>
 __global__ __launch_bounds__(kNT) void k_adjoint(const cplx<R>* __restrict__ zc,
-                                                 const cplx<R>* __restrict__ D,
+                                                 const cplx<double>* __restrict__ D,
                                                  const Moments* __restrict__ mom, Geom g,
                                                  int curve0, double eps,
                                                  const O* __restrict__ gin,
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kNT) void k_adjoint(const cplx<R>* __restrict__ zc,
     } else {
       // Forward spectra at bin k (same unpacking as the solve).
       double Qr[2 * H + 1], Qi[2 * H + 1], Pr[H + 1], Pi[H + 1];
-      const cplx<R> Dk = D[k];
+      const cplx<double> Dk = D[k];
       const double Dr = (double)Dk.x, Di = (double)Dk.y;
       Qr[0] = mo.W;
       Qi[0] = 0.0;
@@ -269,22 +269,28 @@ __global__ __launch_bounds__(kNT) void k_adjoint(const cplx<R>* __restrict__ zc,
   if (tid == 0) dw_part[(int64_t)c * bpc + blockIdx.x] = red[0];
 }
 
-template <typename R>
-__device__ __forceinline__ R es_kernel(R z, R beta) {
-  const R q = (R)1 - z * z;
-  if (!(q > (R)0)) return (R)0;
-  if constexpr (sizeof(R) == 4) {
-    return expf(beta * (sqrtf(q) - 1.0f));
+// Same kernel evaluation as the spreading (FP64 argument; FP32 exponential
+// with its rounding residual corrected unless EXACT).
+template <bool EXACT>
+__device__ __forceinline__ double es_kernel(double z, double beta) {
+  const double q = 1.0 - z * z;
+  if (!(q > 0.0)) return 0.0;
+  const double arg = beta * (sqrt(q) - 1.0);
+  if constexpr (EXACT) {
+    return exp(arg);
   } else {
-    return exp(beta * (sqrt(q) - 1.0));
+    const float a = (float)arg;
+    const double r = arg - (double)a;
+    return (double)expf(a) * (1.0 + r);
   }
 }
 
-template <typename R>
+template <typename S>
 __global__ __launch_bounds__(kNT) void k_gather(const double* __restrict__ t,
                                                 const Moments* __restrict__ mom, Geom g,
-                                                int curve0, const cplx<R>* __restrict__ grid,
+                                                int curve0, const cplx<S>* __restrict__ grid,
                                                 double* __restrict__ gq, double* __restrict__ gp) {
+  constexpr bool EXACT = sizeof(S) == 8;
   const int cw = blockIdx.y;
   const Moments mo = mom[curve0 + cw];
   const int64_t il = (int64_t)blockIdx.x * kNT + threadIdx.x;
@@ -292,34 +298,32 @@ __global__ __launch_bounds__(kNT) void k_gather(const double* __restrict__ t,
   if (mo.flags & kCurveFatal) return;
   const int64_t i = mo.start + il;
   const int hw = g.w / 2;
-  const R two_over_w = (R)(2.0 / (double)g.w);
-  const R beta = (R)g.beta;
+  const double two_over_w = 2.0 / (double)g.w;
   const double v = (t[i] - mo.T0) * g.df;
-  R aq = (R)0, ap = (R)0;
+  double aq = 0.0, ap = 0.0;
   for (int p = 0; p < g.P; ++p) {
-    const cplx<R>* gr = grid + ((int64_t)cw * g.P + p) * g.L;
+    const cplx<S>* gr = grid + ((int64_t)cw * g.P + p) * g.L;
     for (int comp = 0; comp < 2; ++comp) {
       const int m = g.comp_m[p][comp];
       if (m == 0) continue;
       const double pos = ((double)m * v) * (double)g.L + (double)g.c_off;
       const double fl = floor(pos);
       const int64_t j0 = (int64_t)fl;
-      const R fr = (R)(pos - fl);
-      R acc = (R)0;
+      const double fr = pos - fl;
+      double acc = 0.0;
       for (int dj = -hw - 1; dj <= hw + 1; ++dj) {
-        const R dd = (R)dj - fr;  // (j0 + dj) - pos
-        const R phi = es_kernel<R>(dd * two_over_w, beta);
-        if (phi != (R)0) {
-          const cplx<R> val = gr[j0 + dj];
-          acc += phi * (comp == 0 ? val.x : -val.y);
+        const double phi = es_kernel<EXACT>(((double)dj - fr) * two_over_w, g.beta);
+        if (phi != 0.0) {
+          const cplx<S> val = gr[j0 + dj];
+          acc += phi * (comp == 0 ? (double)val.x : -(double)val.y);
         }
       }
       if (g.comp_kind[p][comp] == 0) aq += acc;
       else ap += acc;
     }
   }
-  gq[i] = (double)aq;
-  gp[i] = (double)ap;
+  gq[i] = aq;
+  gp[i] = ap;
 }
 
 __global__ __launch_bounds__(kNT) void k_finalize(const double* __restrict__ x,
@@ -385,7 +389,7 @@ hipError_t adjoint_h(bool fp64, const void* zc, const void* D, const Moments* mo
                        (const double*)gin, (cplx<double>*)spec, dw, bpc);
   else
     hipLaunchKernelGGL((k_adjoint<H, float, float>), gr, dim3(kNT), 0, st,
-                       (const cplx<float>*)zc, (const cplx<float>*)D, mom, g, curve0, eps,
+                       (const cplx<float>*)zc, (const cplx<double>*)D, mom, g, curve0, eps,
                        (const float*)gin, (cplx<float>*)spec, dw, bpc);
   return hipGetLastError();
 }

@@ -25,6 +25,15 @@ struct Moments {
   uint32_t pad;
 };
 
+// Partial moments of one chunk of a curve.
+struct MomPart {
+  double W;       // sum of weights
+  double mean;    // weighted mean of the chunk
+  double M2;      // sum w (x - mean)^2 over the chunk
+  uint32_t bad;   // CF_* validity bits seen in the chunk
+  uint32_t pad;
+};
+
 // Curve flags (also reported in the curve's first output flag byte).
 enum : uint32_t {
   CF_NONFINITE = 1u << 3,  // a non-finite t, x or sigma, or sigma <= 0

@@ -8,7 +8,10 @@
 //   X[k' + (L/N_1) k_1] = sum_{j_1} w_{N_1}^{j_1 k_1} w_L^{j_1 k'} Y_{j_1}[k'],
 //   Y_{j_1} = FFT_{L/N_1}(x[j_1 + N_1 * .]).
 // Passes run from the most significant digit (PASS_FIRST) down to j_1
-// (PASS_LAST).  Every pass is a batch of N_q-point FFTs done in LDS on a tile
+// (PASS_LAST).  Grids are stored in HBM as S (float or double); every tile is
+// held in LDS and transformed in FP64, and the twiddles between passes are
+// formed per workgroup in FP64 from exactly reduced exponents, so HBM storage
+// is the only place a mixed-precision plan rounds to FP32.  Every pass is a batch of N_q-point FFTs done in LDS on a tile
 // of N_q rows x T consecutive columns, so global reads and writes are runs of
 // T (or N_q) consecutive elements.  PASS_FIRST reads the natural-order grid
 // written by the spreading kernel and writes a digit-reversed prefix layout;
@@ -110,91 +113,125 @@ __device__ __forceinline__ void dft_reg(cplx<R>* v) {
 }
 
 constexpr int kNT = 256;  // threads per FFT workgroup
+constexpr int kLE = 12;   // log2 of the tile: 4096 complex elements
+constexpr int kEPT = (1 << kLE) / kNT;  // elements per thread (16)
+using C = cplx<double>;
 
-template <typename R>
-struct TileElems;
-template <>
-struct TileElems<float> {
-  static constexpr int log = 13;  // 8192 complex floats per tile (64 KiB)
-};
-template <>
-struct TileElems<double> {
-  static constexpr int log = 12;  // 4096 complex doubles per tile (64 KiB)
+template <typename S>
+__device__ __forceinline__ C widen(cplx<S> v) {
+  return cmk<double>((double)v.x, (double)v.y);
+}
+template <typename S>
+__device__ __forceinline__ cplx<S> narrow(C v) {
+  return cmk<S>((S)v.x, (S)v.y);
+}
+
+// Stockham stage geometry over a tile of N rows x T columns.  Butterfly bi of
+// thread tid (slot it) is bi = tid + it * kNT: column c = bi % T, butterfly
+// b = bi / T; its element i is input row b + i N / RAD and output row
+// (b / NS) NS RAD + b % NS + i NS.  Every thread holds kEPT elements.
+template <int LOGN, int LOGT, int LOGNS>
+struct Stage {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int T = 1 << LOGT;
+  static constexpr int LOGRAD = (LOGN - LOGNS) >= 4 ? 4 : (LOGN - LOGNS);
+  static constexpr int RAD = 1 << LOGRAD;
+  static constexpr int NS = 1 << LOGNS;
+  static constexpr int PER = kEPT / RAD;
+  static constexpr bool LAST = (LOGNS + LOGRAD) == LOGN;
+  static_assert(PER * RAD == kEPT, "radix must divide the per-thread elements");
+  __device__ static int col(int tid, int it) { return (tid + it * kNT) & (T - 1); }
+  __device__ static int bfly(int tid, int it) { return (tid + it * kNT) >> LOGT; }
+  __device__ static int in_row(int b, int i) { return b + i * (N / RAD); }
+  __device__ static int out_row(int b, int i) {
+    return ((b >> LOGNS) << (LOGNS + LOGRAD)) + (b & (NS - 1)) + i * NS;
+  }
 };
 
-// One Stockham radix-RAD stage over the tile [N rows][T columns] in LDS.
-template <typename R, int LOGN, int LOGT, int LOGNS>
-__device__ __forceinline__ void lds_stage(cplx<R>* sm, const cplx<R>* __restrict__ tw,
-                                          int tid) {
-  constexpr int N = 1 << LOGN;
-  constexpr int T = 1 << LOGT;
-  constexpr int NS = 1 << LOGNS;
-  constexpr int LOGRAD = (LOGN - LOGNS) >= 4 ? 4 : (LOGN - LOGNS);
-  constexpr int RAD = 1 << LOGRAD;
-  constexpr int PT = (T == 1) ? 1 : T + 1;
-  constexpr int NBF = (N / RAD) * T;
-  constexpr int PER = NBF / kNT;
-  static_assert(PER >= 1 && PER * kNT == NBF, "tile too small for the workgroup");
-  constexpr int TWS = kStageLog - LOGNS - LOGRAD;
+// Butterflies of one stage on the registers (FP64): stage twiddles from the
+// omega_{2^13} table, then the in-register RAD-point DFT.
+template <int LOGN, int LOGT, int LOGNS>
+__device__ __forceinline__ void stage_compute(C* v, const C* __restrict__ tw, int tid) {
+  using St = Stage<LOGN, LOGT, LOGNS>;
+  constexpr int TWS = kStageLog - LOGNS - St::LOGRAD;
   static_assert(TWS >= 0, "stage twiddle table too small");
-
-  cplx<R> v[PER][RAD];
 #pragma unroll
-  for (int it = 0; it < PER; ++it) {
-    const int bi = tid + it * kNT;
-    const int c = bi & (T - 1);
-    const int b = bi >> LOGT;
+  for (int it = 0; it < St::PER; ++it) {
+    C* u = v + it * St::RAD;
+    if constexpr (St::NS > 1) {
+      const int j = St::bfly(tid, it) & (St::NS - 1);
 #pragma unroll
-    for (int i = 0; i < RAD; ++i) v[it][i] = sm[(b + i * (N / RAD)) * PT + c];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < PER; ++it) {
-    const int bi = tid + it * kNT;
-    const int c = bi & (T - 1);
-    const int b = bi >> LOGT;
-    const int j = b & (NS - 1);
-    if constexpr (NS > 1) {
-#pragma unroll
-      for (int i = 1; i < RAD; ++i) v[it][i] = cmul(v[it][i], tw[(j * i) << TWS]);
+      for (int i = 1; i < St::RAD; ++i) u[i] = cmul(u[i], tw[(j * i) << TWS]);
     }
-    dft_reg<R, RAD>(v[it]);
-    const int row0 = ((b >> LOGNS) << (LOGNS + LOGRAD)) + j;
+    dft_reg<double, St::RAD>(u);
+  }
+}
+
+// Run the stages from LOGNS on; between stages the registers go through the
+// LDS tile (type S) in Stockham order.  On return v holds the last stage's
+// outputs: element i of slot it is row out_row(b, i) of column col(tid, it).
+template <typename S, int LOGN, int LOGT, int LOGNS>
+__device__ __forceinline__ void run_stages(C* v, cplx<S>* sm, const C* __restrict__ tw,
+                                           int tid) {
+  using St = Stage<LOGN, LOGT, LOGNS>;
+  constexpr int PT = (St::T == 1) ? 1 : St::T + 1;
+  stage_compute<LOGN, LOGT, LOGNS>(v, tw, tid);
+  if constexpr (!St::LAST) {
+    using Nx = Stage<LOGN, LOGT, LOGNS + St::LOGRAD>;
+    __syncthreads();  // previous readers of sm are done
 #pragma unroll
-    for (int i = 0; i < RAD; ++i) sm[(row0 + i * NS) * PT + c] = v[it][i];
+    for (int it = 0; it < St::PER; ++it) {
+      const int c = St::col(tid, it), b = St::bfly(tid, it);
+#pragma unroll
+      for (int i = 0; i < St::RAD; ++i)
+        sm[St::out_row(b, i) * PT + c] = narrow<S>(v[it * St::RAD + i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < Nx::PER; ++it) {
+      const int c = Nx::col(tid, it), b = Nx::bfly(tid, it);
+#pragma unroll
+      for (int i = 0; i < Nx::RAD; ++i)
+        v[it * Nx::RAD + i] = widen(sm[Nx::in_row(b, i) * PT + c]);
+    }
+    run_stages<S, LOGN, LOGT, LOGNS + St::LOGRAD>(v, sm, tw, tid);
   }
-  __syncthreads();
 }
 
-template <typename R, int LOGN, int LOGT, int LOGNS>
-__device__ __forceinline__ void lds_fft(cplx<R>* sm, const cplx<R>* __restrict__ tw, int tid) {
-  if constexpr (LOGNS < LOGN) {
-    lds_stage<R, LOGN, LOGT, LOGNS>(sm, tw, tid);
-    constexpr int step = (LOGN - LOGNS) >= 4 ? 4 : (LOGN - LOGNS);
-    lds_fft<R, LOGN, LOGT, LOGNS + step>(sm, tw, tid);
-  }
+// LOGNS of the last stage: stages advance by radix 16 until the remainder.
+constexpr int last_logns(int logn) {
+  int ns = 0;
+  while (ns + ((logn - ns) >= 4 ? 4 : (logn - ns)) < logn) ns += 4;
+  return ns;
 }
 
-// omega_L^e from the two-level table: lo[e & (2^s - 1)] * hi[e >> s].
-template <typename R>
-__device__ __forceinline__ cplx<R> tw_L(const cplx<R>* __restrict__ lo,
-                                        const cplx<R>* __restrict__ hi, int64_t e, int s) {
-  const int64_t m = ((int64_t)1 << s) - 1;
-  return cmul(lo[e & m], hi[e >> s]);
+// exp(+2 pi i e / 2^logM) for 0 <= e < 2^logM (exact argument reduction).
+__device__ __forceinline__ C root(int64_t e, int logM) {
+  double s, c;
+  sincospi(ldexp((double)e, 1 - logM), &s, &c);
+  return cmk<double>(c, s);
 }
 
-template <typename R, int LOGN, int LOGT>
-__global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<R>* in,
-                                                 cplx<R>* out,
+// One pass.  Twiddles between passes, for output row k of tile column cc:
+//   PASS_FIRST, np >= 3: w_M^{jd k}        (jd fixed for the tile)   = r[k]
+//   PASS_FIRST, np == 2: w_L^{(g0+cc) k}   = r[k] * small[cc k]
+//   PASS_MID:            w_M^{jd (K0+cc+Tail k)}                     = c[cc] r[k]
+// with r, c built per workgroup in FP64 and small[e] = w_L^e, e < 2^kLE.
+template <typename S, int LOGN, int LOGT>
+__global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<S>* in,
+                                                 cplx<S>* out,
                                                  const Moments* __restrict__ mom, Geom g,
-                                                 const cplx<R>* __restrict__ tw_stage,
-                                                 const cplx<R>* __restrict__ tw_lo,
-                                                 const cplx<R>* __restrict__ tw_hi) {
+                                                 const C* __restrict__ tw_stage,
+                                                 const C* __restrict__ tw_small) {
   constexpr int N = 1 << LOGN;
   constexpr int T = 1 << LOGT;
   constexpr int PT = (T == 1) ? 1 : T + 1;
-  constexpr int ELEMS = N * T;
-  __shared__ cplx<R> sm[N * PT];
+  static_assert(N * T == (1 << kLE), "tile size");
+  using S0 = Stage<LOGN, LOGT, 0>;
+  using SL = Stage<LOGN, LOGT, last_logns(LOGN)>;
+  __shared__ cplx<S> sm[N * PT];
+  __shared__ C tr[T == 1 ? 1 : N];  // the single-pass tile has no twiddles
+  __shared__ C tc[T];
 
   const int tid = threadIdx.x;
   const int p = blockIdx.y;
@@ -205,74 +242,97 @@ __global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<R>* 
   const int64_t L = g.L;
   const int logL = a.logL;
   const int64_t grid_off = ((int64_t)cw * g.P + p) * L;
-  const cplx<R>* src = in + grid_off;
+  const cplx<S>* src = in + grid_off;
   const int64_t g0 = (int64_t)blockIdx.x * T;  // first column of this tile
-  const cplx<R> zero = cmk<R>((R)0, (R)0);
 
-  // Sum of log2 N over digits below q.
-  int low_bits = 0;
+  int low_bits = 0;  // sum of log2 N over digits below q
   for (int d = 1; d < a.q; ++d) low_bits += a.logn[d];
 
+  C v[kEPT];
+  // Stage-0 inputs straight from HBM: element i of slot it is row
+  // in_row(b, i) of column col(tid, it).
   if (a.kind == PASS_FIRST || a.kind == PASS_SINGLE) {
-    // Column c = g0 + cc, row r at c + S * r, S = L / N.
-    const int64_t S = L >> LOGN;
+    const int64_t Sd = L >> LOGN;  // column c = g0 + cc, row r at c + Sd r
     int64_t r_skip_lo, r_skip_hi;  // rows in [r_skip_lo, r_skip_hi) are zero
     if (a.mode == MODE_FWD) {
       const int64_t E = pair_extent(mo, g, p);
-      r_skip_lo = (E + S - 1) / S;
+      r_skip_lo = (E + Sd - 1) / Sd;
       r_skip_hi = N;
     } else {
-      r_skip_lo = g.n_freq / S;
-      r_skip_hi = (L - g.n_freq) / S;
+      r_skip_lo = g.n_freq / Sd;
+      r_skip_hi = (L - g.n_freq) / Sd;
     }
-#pragma unroll 4
-    for (int it = 0; it < ELEMS / kNT; ++it) {
-      const int e = tid + it * kNT;
-      const int cc = e & (T - 1);
-      const int r = e >> LOGT;
-      cplx<R> v = zero;
-      if (r < r_skip_lo || r >= r_skip_hi) v = src[g0 + cc + S * r];
-      sm[r * PT + cc] = v;
+#pragma unroll
+    for (int it = 0; it < S0::PER; ++it) {
+      const int cc = S0::col(tid, it), b = S0::bfly(tid, it);
+#pragma unroll
+      for (int i = 0; i < S0::RAD; ++i) {
+        const int r = S0::in_row(b, i);
+        C val = cmk<double>(0.0, 0.0);
+        if (r < r_skip_lo || r >= r_skip_hi) val = widen(src[g0 + cc + Sd * r]);
+        v[it * S0::RAD + i] = val;
+      }
     }
-  } else if (a.kind == PASS_MID) {
+    if (a.kind == PASS_FIRST) {
+      const int np = a.np;
+      const int logM = a.logn[np - 1] + LOGN;
+      if (np >= 3) {
+        int bits_below = 0;
+        for (int d = 1; d < np - 1; ++d) bits_below += a.logn[d];
+        const int64_t jd = g0 >> bits_below;
+        const int64_t Mmask = ((int64_t)1 << logM) - 1;
+        for (int k = tid; k < N; k += kNT) tr[k] = root((jd * k) & Mmask, logM);
+      } else {
+        for (int k = tid; k < N; k += kNT) tr[k] = root((g0 * k) & (L - 1), logL);
+      }
+    }
+  } else {
+    // PASS_MID: column (pre, K0 + cc), row r at pre N Tail + r Tail + K0 + cc.
+    // PASS_LAST: pre = 0, Tail = L / N.
     const int64_t Tail = L >> (low_bits + LOGN);
     const int64_t pre = g0 / Tail;
     const int64_t K0 = g0 - pre * Tail;
-    const cplx<R>* base = src + pre * ((int64_t)N * Tail) + K0;
-#pragma unroll 4
-    for (int it = 0; it < ELEMS / kNT; ++it) {
-      const int e = tid + it * kNT;
-      const int cc = e & (T - 1);
-      const int r = e >> LOGT;
-      sm[r * PT + cc] = base[r * Tail + cc];
+    const cplx<S>* base = src + pre * ((int64_t)N * Tail) + K0;
+#pragma unroll
+    for (int it = 0; it < S0::PER; ++it) {
+      const int cc = S0::col(tid, it), b = S0::bfly(tid, it);
+#pragma unroll
+      for (int i = 0; i < S0::RAD; ++i)
+        v[it * S0::RAD + i] = widen(base[(int64_t)S0::in_row(b, i) * Tail + cc]);
     }
-  } else {  // PASS_LAST
-    const int64_t Tail = L >> LOGN;
-    const cplx<R>* base = src + g0;
-#pragma unroll 4
-    for (int it = 0; it < ELEMS / kNT; ++it) {
-      const int e = tid + it * kNT;
-      const int cc = e & (T - 1);
-      const int r = e >> LOGT;
-      sm[r * PT + cc] = base[r * Tail + cc];
+    if (a.kind == PASS_MID) {
+      const int64_t jd = pre & (((int64_t)1 << a.logn[a.q - 1]) - 1);
+      const int logTail = logL - low_bits - LOGN;
+      const int logM = a.logn[a.q - 1] + LOGN + logTail;
+      const int64_t Mmask = ((int64_t)1 << logM) - 1;
+      for (int k = tid; k < N; k += kNT) tr[k] = root((jd * Tail * k) & Mmask, logM);
+      for (int cc = tid; cc < T; cc += kNT) tc[cc] = root((jd * (K0 + cc)) & Mmask, logM);
     }
   }
-  __syncthreads();
+  // tr/tc become visible at the first barrier inside run_stages, or below.
+  run_stages<S, LOGN, LOGT, 0>(v, sm, tw_stage, tid);
+  if constexpr (last_logns(LOGN) == 0) __syncthreads();  // single-stage tile
 
-  lds_fft<R, LOGN, LOGT, 0>(sm, tw_stage, tid);
-
-  cplx<R>* dst = out + grid_off;
+  cplx<S>* dst = out + grid_off;
   if (a.kind == PASS_FIRST) {
-    // Output row for column c is rev(c) * N + k (digit-reversed prefix).
+    // Twiddle in registers, then transpose through LDS so that each column's
+    // N outputs leave as one contiguous run at row rev(c) of the output.
     const int np = a.np;
-    // Twiddle digit j_{np-1} = c >> (bits of digits 1..np-2); modulus N_{np-1} * N.
-    int bits_below = 0;
-    for (int d = 1; d < np - 1; ++d) bits_below += a.logn[d];
-    const int logM = a.logn[np - 1] + LOGN;
-    const int64_t Mmask = ((int64_t)1 << logM) - 1;
-    const int sh = logL - logM;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SL::PER; ++it) {
+      const int cc = SL::col(tid, it), b = SL::bfly(tid, it);
+#pragma unroll
+      for (int i = 0; i < SL::RAD; ++i) {
+        const int k = SL::out_row(b, i);
+        C tw = tr[k];
+        if (np == 2) tw = cmul(tw, tw_small[cc * k]);
+        sm[k * PT + cc] = narrow<S>(cmul(v[it * SL::RAD + i], tw));
+      }
+    }
+    __syncthreads();
 #pragma unroll 4
-    for (int it = 0; it < ELEMS / kNT; ++it) {
+    for (int it = 0; it < kEPT; ++it) {
       const int e = tid + it * kNT;
       const int k = e & (N - 1);
       const int cc = e >> LOGN;
@@ -284,111 +344,97 @@ __global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<R>* 
         rest >>= a.logn[d];
         rev = (rev << a.logn[d]) | dig;
       }
-      cplx<R> v = sm[k * PT + cc];
-      const int64_t jd = c >> bits_below;
-      const int64_t ex = ((jd * (int64_t)k) & Mmask) << sh;
-      v = cmul(v, tw_L(tw_lo, tw_hi, ex, a.tw_s));
-      dst[rev * N + k] = v;
+      dst[rev * N + k] = sm[k * PT + cc];
     }
   } else if (a.kind == PASS_MID) {
     const int64_t Tail = L >> (low_bits + LOGN);
     const int64_t pre = g0 / Tail;
     const int64_t K0 = g0 - pre * Tail;
-    const int64_t jd = pre & (((int64_t)1 << a.logn[a.q - 1]) - 1);
-    int logTail = logL - low_bits - LOGN;
-    const int logM = a.logn[a.q - 1] + LOGN + logTail;
-    const int64_t Mmask = ((int64_t)1 << logM) - 1;
-    const int sh = logL - logM;
-    cplx<R>* base = dst + pre * ((int64_t)N * Tail) + K0;
-#pragma unroll 4
-    for (int it = 0; it < ELEMS / kNT; ++it) {
-      const int e = tid + it * kNT;
-      const int cc = e & (T - 1);
-      const int k = e >> LOGT;
-      const int64_t Kp = K0 + cc + Tail * k;
-      const int64_t ex = ((jd * Kp) & Mmask) << sh;
-      base[k * Tail + cc] = cmul(sm[k * PT + cc], tw_L(tw_lo, tw_hi, ex, a.tw_s));
+    cplx<S>* base = dst + pre * ((int64_t)N * Tail) + K0;
+#pragma unroll
+    for (int it = 0; it < SL::PER; ++it) {
+      const int cc = SL::col(tid, it), b = SL::bfly(tid, it);
+      const C fc = tc[cc];
+#pragma unroll
+      for (int i = 0; i < SL::RAD; ++i) {
+        const int k = SL::out_row(b, i);
+        base[(int64_t)k * Tail + cc] = narrow<S>(cmul(v[it * SL::RAD + i], cmul(fc, tr[k])));
+      }
     }
   } else {
     // PASS_LAST / PASS_SINGLE: X index = K + Tail * k, natural order.
     const int64_t Tail = L >> LOGN;
     const int64_t nf = g.n_freq;
     if (a.mode == MODE_FWD) {
-      cplx<R>* z0 = (cplx<R>*)a.zc + ((int64_t)cw * g.P + p) * 2 * nf;
-      cplx<R>* z1 = z0 + nf;
-#pragma unroll 4
-      for (int it = 0; it < ELEMS / kNT; ++it) {
-        const int e = tid + it * kNT;
-        const int cc = e & (T - 1);
-        const int k = e >> LOGT;
-        const int64_t X = g0 + cc + Tail * k;
-        const cplx<R> v = sm[k * PT + cc];
-        if (X < nf) z0[X] = v;
-        const int64_t Xm = (L - X) & (L - 1);
-        if (Xm < nf) z1[Xm] = v;
+      cplx<S>* z0 = (cplx<S>*)a.zc + ((int64_t)cw * g.P + p) * 2 * nf;
+      cplx<S>* z1 = z0 + nf;
+#pragma unroll
+      for (int it = 0; it < SL::PER; ++it) {
+        const int cc = SL::col(tid, it), b = SL::bfly(tid, it);
+#pragma unroll
+        for (int i = 0; i < SL::RAD; ++i) {
+          const int64_t X = g0 + cc + Tail * SL::out_row(b, i);
+          const cplx<S> val = narrow<S>(v[it * SL::RAD + i]);
+          if (X < nf) z0[X] = val;
+          const int64_t Xm = (L - X) & (L - 1);
+          if (Xm < nf) z1[Xm] = val;
+        }
       }
     } else {
       const int64_t E = pair_extent(mo, g, p);
-#pragma unroll 4
-      for (int it = 0; it < ELEMS / kNT; ++it) {
-        const int e = tid + it * kNT;
-        const int cc = e & (T - 1);
-        const int k = e >> LOGT;
-        const int64_t X = g0 + cc + Tail * k;
-        if (X < E) ((cplx<R>*)a.grid_out)[grid_off + X] = sm[k * PT + cc];
+      cplx<S>* go = (cplx<S>*)a.grid_out + grid_off;
+#pragma unroll
+      for (int it = 0; it < SL::PER; ++it) {
+        const int cc = SL::col(tid, it), b = SL::bfly(tid, it);
+#pragma unroll
+        for (int i = 0; i < SL::RAD; ++i) {
+          const int64_t X = g0 + cc + Tail * SL::out_row(b, i);
+          if (X < E) go[X] = narrow<S>(v[it * SL::RAD + i]);
+        }
       }
     }
   }
 }
 
-template <typename R, int LOGN, int LOGT>
+template <typename S, int LOGN, int LOGT>
 hipError_t launch_one(const FftPassArgs& a, const void* in, void* out, const Moments* mom,
-                      const Geom& g, const void* tws, const void* twl, const void* twh,
-                      int n_curves, int64_t ncols, hipStream_t st) {
+                      const Geom& g, const void* tws, const void* twsm, int n_curves,
+                      int64_t ncols, hipStream_t st) {
   dim3 grid((unsigned)(ncols >> LOGT), (unsigned)g.P, (unsigned)n_curves);
-  hipLaunchKernelGGL((k_fft_pass<R, LOGN, LOGT>), grid, dim3(kNT), 0, st, a,
-                     (const cplx<R>*)in, (cplx<R>*)out, mom, g, (const cplx<R>*)tws,
-                     (const cplx<R>*)twl, (const cplx<R>*)twh);
+  hipLaunchKernelGGL((k_fft_pass<S, LOGN, LOGT>), grid, dim3(kNT), 0, st, a,
+                     (const cplx<S>*)in, (cplx<S>*)out, mom, g, (const C*)tws, (const C*)twsm);
   return hipGetLastError();
 }
 
-template <typename R>
+template <typename S>
 hipError_t dispatch(const FftPassArgs& a, int logn, int logt, const void* in, void* out,
-                    const Moments* mom, const Geom& g, const void* tws, const void* twl,
-                    const void* twh, int n_curves, int64_t ncols, hipStream_t st) {
-  constexpr int LE = TileElems<R>::log;
+                    const Moments* mom, const Geom& g, const void* tws, const void* twsm,
+                    int n_curves, int64_t ncols, hipStream_t st) {
   if (logt == 0) {
-    // Single-pass tile: the whole grid in one workgroup.
-    if (logn == LE) return launch_one<R, LE, 0>(a, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
-    if constexpr (LE - 1 >= 12) {
-      if (logn == LE - 1) return launch_one<R, LE - 1, 0>(a, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
-    }
+    if (logn == kLE) return launch_one<S, kLE, 0>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
     return hipErrorInvalidValue;
   }
-  if (logn + logt != LE) return hipErrorInvalidValue;
+  if (logn + logt != kLE) return hipErrorInvalidValue;
   switch (logn) {
-    case 4: return launch_one<R, 4, LE - 4>(a, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
-    case 5: return launch_one<R, 5, LE - 5>(a, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
-    case 6: return launch_one<R, 6, LE - 6>(a, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
-    case 7: return launch_one<R, 7, LE - 7>(a, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
-    case 8: return launch_one<R, 8, LE - 8>(a, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
-    case 9: return launch_one<R, 9, LE - 9>(a, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
-    case 10: return launch_one<R, 10, LE - 10>(a, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
+    case 4: return launch_one<S, 4, kLE - 4>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+    case 5: return launch_one<S, 5, kLE - 5>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+    case 6: return launch_one<S, 6, kLE - 6>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+    case 7: return launch_one<S, 7, kLE - 7>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+    case 8: return launch_one<S, 8, kLE - 8>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+    case 9: return launch_one<S, 9, kLE - 9>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-int fft_tile_log(bool fp64) { return fp64 ? TileElems<double>::log : TileElems<float>::log; }
+int fft_tile_log() { return kLE; }
 
 hipError_t launch_fft_pass(bool fp64, const FftPassArgs& a, int logn, int logt, const void* in,
                            void* out, const Moments* mom, const Geom& g, const void* tws,
-                           const void* twl, const void* twh, int n_curves, int64_t ncols,
-                           hipStream_t st) {
-  if (fp64)
-    return dispatch<double>(a, logn, logt, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
-  return dispatch<float>(a, logn, logt, in, out, mom, g, tws, twl, twh, n_curves, ncols, st);
+                           const void* twsm, int n_curves, int64_t ncols, hipStream_t st) {
+  if (fp64) return dispatch<double>(a, logn, logt, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+  return dispatch<float>(a, logn, logt, in, out, mom, g, tws, twsm, n_curves, ncols, st);
 }
 
 }  // namespace fchi2

@@ -2,6 +2,7 @@
 // layout and the launch sequence of the search and its adjoint.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -81,7 +82,7 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
-// Choose the FFT digit split of L = 2^logL into np passes of radix <= 2^10.
+// Choose the FFT digit split of L = 2^logL into np passes of radix <= 2^9.
 // Constraints: each pass tile holds 2^LE elements as N_q rows x T columns and
 // the T columns of one tile must share their other digits.
 bool plan_fft(int logL, int LE, FftPlan& fp) {
@@ -96,8 +97,9 @@ bool plan_fft(int logL, int LE, FftPlan& fp) {
     int best_min = -1;
     int best[kMaxPasses + 1] = {0};
     int ln[kMaxPasses + 1];
-    // Enumerate compositions of logL into np parts in [4, 10].
-    const int lo = 4, hi = 10;
+    // Enumerate compositions of logL into np parts in [4, 9] (a tile then has
+    // at least 8 columns, so global accesses are runs of >= 64 bytes).
+    const int lo = 4, hi = 9;
     int total = 1;
     for (int q = 0; q < np; ++q) total *= (hi - lo + 1);
     for (int code = 0; code < total; ++code) {
@@ -138,6 +140,44 @@ bool plan_fft(int logL, int LE, FftPlan& fp) {
   return false;
 }
 
+// Every valid digit split of L = 2^logL with the smallest pass count
+// (more passes only add HBM traffic).
+std::vector<FftPlan> fft_splits(int logL, int LE) {
+  std::vector<FftPlan> out;
+  FftPlan best{};
+  if (!plan_fft(logL, LE, best)) return out;
+  if (best.np == 1) {
+    out.push_back(best);
+    return out;
+  }
+  const int np = best.np, lo = 4, hi = 9;
+  int total = 1;
+  for (int q = 0; q < np; ++q) total *= (hi - lo + 1);
+  int ln[kMaxPasses + 1];
+  for (int code = 0; code < total; ++code) {
+    int c = code, sum = 0;
+    for (int q = 1; q <= np; ++q) {
+      ln[q] = lo + c % (hi - lo + 1);
+      c /= (hi - lo + 1);
+      sum += ln[q];
+    }
+    if (sum != logL) continue;
+    bool ok = LE - ln[np] <= ln[1];
+    for (int q = 2; q < np && ok; ++q) {
+      int tail = 0;
+      for (int d = q + 1; d <= np; ++d) tail += ln[d];
+      if (LE - ln[q] > tail) ok = false;
+    }
+    if (!ok) continue;
+    FftPlan f{};
+    f.np = np;
+    f.logL = logL;
+    for (int q = 1; q <= np; ++q) f.logn[q] = ln[q];
+    out.push_back(f);
+  }
+  return out;
+}
+
 }  // namespace
 
 struct fchi2_plan_s {
@@ -148,19 +188,21 @@ struct fchi2_plan_s {
   size_t out_elem = 4;    // bytes per Delta chi2 value
   Geom g{};
   FftPlan fp{};
-  int tw_s = 0;
   int log_tile = 10;
   double eps_piv = 0.0;
   int wave = 1;
+  int wave_max = 1;        // the workspace is sized for this many curves
+  int64_t max_n = 0;
   int64_t n_total = 0;
   // plan-owned device tables
   int64_t* d_off = nullptr;
   void* d_tw_stage = nullptr;
-  void* d_tw_lo = nullptr;
-  void* d_tw_hi = nullptr;
+  void* d_tw_small = nullptr;
   void* d_D = nullptr;
   double* d_gl = nullptr;
   // workspace layout (byte offsets)
+  int mom_bpc = 1;
+  size_t off_part = 0;
   size_t off_mom = 0, off_gA = 0, off_gB = 0, off_zc = 0, off_gq = 0, off_gp = 0, off_dw = 0;
   size_t ws_bytes = 0;
   int blocks_per_curve = 0;
@@ -170,29 +212,70 @@ struct fchi2_plan_s {
   size_t gkey_ws = 0;
   // backward needs a search on this workspace first
   const void* last_ws = nullptr;
+  // measurement: event pairs around each launch while profiling is on
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_stage;
+  double prof_ms[FCHI2_PROF_STAGES] = {0};
+  int64_t prof_n[FCHI2_PROF_STAGES] = {0};
 };
 
 namespace {
 
+void apply_fft_plan(fchi2_plan_s* pl, const FftPlan& f) {
+  pl->fp = f;
+  const int64_t S_first = (f.np == 1) ? 1 : (pl->g.L >> f.logn[f.np]);
+  const int64_t tile = (int64_t)1 << pl->log_tile;
+  pl->g.chunk = (int)(S_first > tile ? S_first : tile);
+}
+
+// Record an event on st if profiling (begin of a launch of `stage` when
+// stage >= 0, its end when stage < 0).
+hipError_t prof_mark(fchi2_plan_s* pl, int stage, hipStream_t st) {
+  if (!pl->prof) return hipSuccess;
+  if (pl->ev_used == pl->ev_pool.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    pl->ev_pool.push_back(e);
+  }
+  hipEvent_t e = pl->ev_pool[pl->ev_used++];
+  if (stage >= 0) pl->ev_stage.push_back(stage);
+  return hipEventRecord(e, st);
+}
+
+#define PROF_BEGIN(stage)                                              \
+  do {                                                                 \
+    hipError_t pe_ = prof_mark(pl, (stage), st);                       \
+    if (pe_ != hipSuccess) return hip_fail(pe_, "profiling event");    \
+  } while (0)
+#define PROF_END()                                                     \
+  do {                                                                 \
+    hipError_t pe_ = prof_mark(pl, -1, st);                            \
+    if (pe_ != hipSuccess) return hip_fail(pe_, "profiling event");    \
+  } while (0)
+
 fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void* zc,
                            const Moments* mom, int curve0, int nw, hipStream_t st) {
   const FftPlan& fp = pl->fp;
-  const int LE = fft_tile_log(pl->fp64);
+  const int LE = fft_tile_log();
   FftPassArgs a{};
   a.mode = mode;
   a.np = fp.np;
   for (int q = 0; q <= kMaxPasses; ++q) a.logn[q] = fp.logn[q];
   a.logL = fp.logL;
-  a.tw_s = pl->tw_s;
   a.curve0 = curve0;
   a.zc = zc;
   a.grid_out = gA;
   if (fp.np == 1) {
     a.kind = PASS_SINGLE;
     a.q = 1;
+    PROF_BEGIN(mode == MODE_FWD ? FCHI2_PROF_FFT_LAST : FCHI2_PROF_BWD_FFT);
     hipError_t e = launch_fft_pass(pl->fp64, a, fp.logL, 0, gA, gA, mom, pl->g, pl->d_tw_stage,
-                                   pl->d_tw_lo, pl->d_tw_hi, nw, 1, st);
+                                   pl->d_tw_small, nw, 1, st);
     if (e != hipSuccess) return hip_fail(e, "fft single pass");
+    PROF_END();
     return FCHI2_OK;
   }
   for (int q = fp.np; q >= 1; --q) {
@@ -203,32 +286,47 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
     const int64_t ncols = pl->g.L >> logn;
     const void* in = (q == fp.np) ? gA : gB;
     void* out = gB;
+    const int stage = mode == MODE_BWD ? FCHI2_PROF_BWD_FFT
+                      : a.kind == PASS_FIRST ? FCHI2_PROF_FFT_FIRST
+                      : a.kind == PASS_MID   ? FCHI2_PROF_FFT_MID
+                                             : FCHI2_PROF_FFT_LAST;
+    PROF_BEGIN(stage);
     hipError_t e = launch_fft_pass(pl->fp64, a, logn, logt, in, out, mom, pl->g, pl->d_tw_stage,
-                                   pl->d_tw_lo, pl->d_tw_hi, nw, ncols, st);
+                                   pl->d_tw_small, nw, ncols, st);
     if (e != hipSuccess) return hip_fail(e, "fft pass");
+    PROF_END();
   }
   return FCHI2_OK;
 }
 
-fchi2_status_t enqueue_search(fchi2_plan_s* pl, const double* t, const double* x,
-                              const double* sigma, char* ws, void* dchi2, double* chi2_0,
-                              uint8_t* flags, hipStream_t st) {
+// The whole forward chain for curves [cbeg, cend), in waves of pl->wave.
+fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double* t,
+                              const double* x, const double* sigma, char* ws, void* dchi2,
+                              double* chi2_0, uint8_t* flags, hipStream_t st) {
   Moments* mom = (Moments*)(ws + pl->off_mom);
-  hipError_t e = launch_moments(t, x, sigma, pl->d_off, pl->desc.n_curves, pl->g, mom, chi2_0, st);
+  PROF_BEGIN(FCHI2_PROF_MOMENTS);
+  hipError_t e = launch_moments(t, x, sigma, pl->d_off + cbeg, cend - cbeg, pl->mom_bpc, pl->g,
+                                (MomPart*)(ws + pl->off_part) + (size_t)cbeg * pl->mom_bpc,
+                                mom + cbeg, chi2_0 ? chi2_0 + cbeg : nullptr, st);
   if (e != hipSuccess) return hip_fail(e, "moments");
+  PROF_END();
   const bool keep = pl->desc.flags & FCHI2_KEEP_FOR_BACKWARD;
   const size_t zc_curve = (size_t)pl->g.P * 2 * pl->g.n_freq * pl->elem;
-  for (int c0 = 0; c0 < pl->desc.n_curves; c0 += pl->wave) {
-    const int nw = (pl->desc.n_curves - c0) < pl->wave ? (pl->desc.n_curves - c0) : pl->wave;
+  for (int c0 = cbeg; c0 < cend; c0 += pl->wave) {
+    const int nw = (cend - c0) < pl->wave ? (cend - c0) : pl->wave;
     void* gA = ws + pl->off_gA;
     void* gB = ws + pl->off_gB;
     void* zc = ws + pl->off_zc + (keep ? (size_t)c0 * zc_curve : 0);
+    PROF_BEGIN(FCHI2_PROF_SPREAD);
     e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, gA, pl->log_tile, st);
     if (e != hipSuccess) return hip_fail(e, "spread");
+    PROF_END();
     fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st);
     if (s != FCHI2_OK) return s;
+    PROF_BEGIN(FCHI2_PROF_SOLVE);
     e = launch_solve(pl->fp64, zc, pl->d_D, mom, pl->g, c0, nw, pl->eps_piv, dchi2, flags, st);
     if (e != hipSuccess) return hip_fail(e, "solve");
+    PROF_END();
   }
   return FCHI2_OK;
 }
@@ -299,7 +397,7 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   g.n_freq = d.n_freq;
   g.L = 4 * d.n_freq;
   g.df = d.f_max / (double)d.n_freq;
-  g.w = d.kernel_width ? d.kernel_width : (pl->fp64 ? 14 : 8);
+  g.w = d.kernel_width ? d.kernel_width : (pl->fp64 ? 14 : 10);
   g.half_w = 0.5 * g.w;
   g.beta = 2.30 * g.w;
   g.c_off = g.w / 2 + 2;
@@ -326,15 +424,12 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     }
   }
   const int logL = ilog2(g.L);
-  if (!plan_fft(logL, fft_tile_log(pl->fp64), pl->fp)) {
+  if (!plan_fft(logL, fft_tile_log(), pl->fp)) {
     delete pl;
     return fail(FCHI2_ERR_UNSUPPORTED, "no FFT pass split for L = 2^%d", logL);
   }
-  pl->tw_s = (logL + 1) / 2;
   pl->log_tile = 10;
-  const int64_t S_first = (pl->fp.np == 1) ? 1 : (g.L >> pl->fp.logn[pl->fp.np]);
-  const int64_t tile = (int64_t)1 << pl->log_tile;
-  g.chunk = (int)(S_first > tile ? S_first : tile);
+  apply_fft_plan(pl, pl->fp);
 
   // Waves: bound the two grid buffers to ~8 GiB unless the caller chose.
   const size_t grid_curve = (size_t)g.P * (size_t)g.L * pl->elem;
@@ -345,12 +440,22 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     if (cap < 1) cap = 1;
     pl->wave = (int)(cap < (size_t)d.n_curves ? cap : (size_t)d.n_curves);
   }
+  pl->wave_max = pl->wave;
   const bool keep = d.flags & FCHI2_KEEP_FOR_BACKWARD;
   const size_t zc_curve = (size_t)g.P * 2 * (size_t)g.n_freq * pl->elem;
   pl->blocks_per_curve = (int)((g.n_freq + 255) / 256);
+  int64_t max_n = 0;
+  for (int c = 0; c < d.n_curves; ++c) {
+    const int64_t n = pl->offsets[c + 1] - pl->offsets[c];
+    max_n = n > max_n ? n : max_n;
+  }
+  pl->max_n = max_n;
+  pl->mom_bpc = (int)std::min<int64_t>(256, std::max<int64_t>(1, (max_n + 4095) / 4096));
   size_t off = 0;
   pl->off_mom = off;
   off = align256(off + sizeof(Moments) * (size_t)d.n_curves);
+  pl->off_part = off;
+  off = align256(off + sizeof(MomPart) * (size_t)d.n_curves * pl->mom_bpc);
   pl->off_gA = off;
   off = align256(off + grid_curve * pl->wave);
   pl->off_gB = off;
@@ -377,46 +482,25 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     return hipMalloc(p, bytes) == hipSuccess;
   };
   const int LT = 1 << kStageLog;
-  const int64_t nlo = (int64_t)1 << pl->tw_s, nhi = g.L >> pl->tw_s;
+  const int64_t NSM = (int64_t)1 << fft_tile_log();
   const int n_gl = 128;
   if (!dev_alloc((void**)&pl->d_off, sizeof(int64_t) * (d.n_curves + 1)) ||
-      !dev_alloc(&pl->d_tw_stage, pl->elem * LT) || !dev_alloc(&pl->d_tw_lo, pl->elem * nlo) ||
-      !dev_alloc(&pl->d_tw_hi, pl->elem * nhi) || !dev_alloc(&pl->d_D, pl->elem * g.n_freq) ||
+      !dev_alloc(&pl->d_tw_stage, 16 * (size_t)LT) ||
+      !dev_alloc(&pl->d_tw_small, 16 * (size_t)NSM) ||
+      !dev_alloc(&pl->d_D, 16 * (size_t)g.n_freq) ||
       !dev_alloc((void**)&pl->d_gl, sizeof(double) * n_gl)) {
     (void)hipGetLastError();
     return cleanup_fail(fail(FCHI2_ERR_NOMEM, "plan table allocation failed"));
   }
-  std::vector<char> hs(pl->elem * LT), hl(pl->elem * nlo), hh(pl->elem * nhi);
-  auto put = [&](std::vector<char>& v, int64_t i, double re, double im) {
-    if (pl->fp64) {
-      double* p = (double*)v.data();
-      p[2 * i] = re;
-      p[2 * i + 1] = im;
-    } else {
-      float* p = (float*)v.data();
-      p[2 * i] = (float)re;
-      p[2 * i + 1] = (float)im;
-    }
-  };
-  auto root = [](int64_t e, int64_t n, double& re, double& im) {
-    // exp(+2 pi i e / n) with the angle reduced to the first octant.
+  // FP64 twiddle tables: omega_{2^13}^e and omega_L^e for e < 2^tile.
+  std::vector<double> hs(2 * (size_t)LT), hsm(2 * (size_t)NSM);
+  auto root = [](int64_t e, int64_t n, double* out2) {
     const long double ang = 2.0L * (long double)M_PI * (long double)(e % n) / (long double)n;
-    re = (double)std::cos(ang);
-    im = (double)std::sin(ang);
+    out2[0] = (double)std::cos(ang);
+    out2[1] = (double)std::sin(ang);
   };
-  double re, im;
-  for (int64_t e = 0; e < LT; ++e) {
-    root(e, LT, re, im);
-    put(hs, e, re, im);
-  }
-  for (int64_t e = 0; e < nlo; ++e) {
-    root(e, g.L, re, im);
-    put(hl, e, re, im);
-  }
-  for (int64_t e = 0; e < nhi; ++e) {
-    root(e << pl->tw_s, g.L, re, im);
-    put(hh, e, re, im);
-  }
+  for (int64_t e = 0; e < LT; ++e) root(e, LT, &hs[2 * e]);
+  for (int64_t e = 0; e < NSM; ++e) root(e, g.L, &hsm[2 * e]);
   std::vector<double> gx, gw, gl(n_gl);
   gauss_legendre(n_gl, gx, gw);
   // Positive nodes; weights fold in the kernel value and the factor w.
@@ -429,15 +513,13 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   hipError_t e;
   if ((e = hipMemcpyAsync(pl->d_off, pl->offsets.data(), sizeof(int64_t) * (d.n_curves + 1),
                           hipMemcpyHostToDevice, st)) != hipSuccess ||
-      (e = hipMemcpyAsync(pl->d_tw_stage, hs.data(), hs.size(), hipMemcpyHostToDevice, st)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(pl->d_tw_lo, hl.data(), hl.size(), hipMemcpyHostToDevice, st)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(pl->d_tw_hi, hh.data(), hh.size(), hipMemcpyHostToDevice, st)) !=
-          hipSuccess ||
+      (e = hipMemcpyAsync(pl->d_tw_stage, hs.data(), sizeof(double) * hs.size(),
+                          hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(pl->d_tw_small, hsm.data(), sizeof(double) * hsm.size(),
+                          hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemcpyAsync(pl->d_gl, gl.data(), sizeof(double) * n_gl, hipMemcpyHostToDevice,
                           st)) != hipSuccess ||
-      (e = launch_deconv_init(pl->fp64, pl->d_D, g, pl->d_gl, pl->d_gl + n_gl / 2, n_gl / 2,
+      (e = launch_deconv_init(pl->d_D, g, pl->d_gl, pl->d_gl + n_gl / 2, n_gl / 2,
                               st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess) {
     return cleanup_fail(hip_fail(e, "plan table setup"));
@@ -462,7 +544,7 @@ fchi2_status_t fchi2_search(fchi2_plan_t plan, const double* t, const double* x,
   char* ws = (char*)workspace;
   plan->last_ws = workspace;
 
-  if ((plan->desc.flags & FCHI2_GRAPH) && st != nullptr) {
+  if ((plan->desc.flags & FCHI2_GRAPH) && st != nullptr && !plan->prof) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIPCHK(hipStreamIsCapturing(st, &cs));
     if (cs == hipStreamCaptureStatusNone) {
@@ -475,7 +557,8 @@ fchi2_status_t fchi2_search(fchi2_plan_t plan, const double* t, const double* x,
           plan->gexec = nullptr;
         }
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        fchi2_status_t es = enqueue_search(plan, t, x, sigma, ws, dchi2, chi2_0, flags, st);
+        fchi2_status_t es =
+            enqueue_search(plan, 0, plan->desc.n_curves, t, x, sigma, ws, dchi2, chi2_0, flags, st);
         hipGraph_t graph = nullptr;
         hipError_t ee = hipStreamEndCapture(st, &graph);
         if (es != FCHI2_OK) {
@@ -496,7 +579,25 @@ fchi2_status_t fchi2_search(fchi2_plan_t plan, const double* t, const double* x,
       return FCHI2_OK;
     }
   }
-  return enqueue_search(plan, t, x, sigma, ws, dchi2, chi2_0, flags, st);
+  return enqueue_search(plan, 0, plan->desc.n_curves, t, x, sigma, ws, dchi2, chi2_0, flags, st);
+}
+
+fchi2_status_t fchi2_search_curves(fchi2_plan_t plan, int32_t first, int32_t count,
+                                   const double* t, const double* x, const double* sigma,
+                                   void* workspace, size_t workspace_bytes, void* dchi2,
+                                   double* chi2_0, uint8_t* flags, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
+  if (!t || !x || !sigma || !dchi2) return fail(FCHI2_ERR_ARG, "t, x, sigma and dchi2 must not be NULL");
+  if (first < 0 || count < 1 || (int64_t)first + count > plan->desc.n_curves)
+    return fail(FCHI2_ERR_ARG, "curve range [%d, %d) outside 0..%d", first, first + count,
+                plan->desc.n_curves);
+  fchi2_status_t s = check_ws(plan, workspace, workspace_bytes);
+  if (s != FCHI2_OK) return s;
+  // Only a search over every curve leaves a state fchi2_backward can use.
+  plan->last_ws = (first == 0 && count == plan->desc.n_curves) ? workspace : nullptr;
+  return enqueue_search(plan, first, first + count, t, x, sigma, (char*)workspace, dchi2, chi2_0,
+                        flags, (hipStream_t)stream);
 }
 
 fchi2_status_t fchi2_backward(fchi2_plan_t plan, const double* t, const double* x,
@@ -514,6 +615,7 @@ fchi2_status_t fchi2_backward(fchi2_plan_t plan, const double* t, const double* 
   if (plan->last_ws != workspace)
     return fail(FCHI2_ERR_STATE, "fchi2_search has not run on this workspace");
   hipStream_t st = (hipStream_t)stream;
+  fchi2_plan_s* pl = plan;
   char* ws = (char*)workspace;
   Moments* mom = (Moments*)(ws + plan->off_mom);
   const size_t zc_curve = (size_t)plan->g.P * 2 * plan->g.n_freq * plan->elem;
@@ -525,10 +627,12 @@ fchi2_status_t fchi2_backward(fchi2_plan_t plan, const double* t, const double* 
     void* gA = ws + plan->off_gA;
     void* gB = ws + plan->off_gB;
     const void* zc = ws + plan->off_zc + (size_t)c0 * zc_curve;
+    PROF_BEGIN(FCHI2_PROF_BWD_SOLVE);
     hipError_t e = launch_adjoint_solve(plan->fp64, zc, plan->d_D, mom, plan->g, c0, nw,
                                         plan->eps_piv, grad_dchi2, gA, dw,
                                         plan->blocks_per_curve, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint solve");
+    PROF_END();
     s = enqueue_fft(plan, MODE_BWD, gA, gB, nullptr, mom, c0, nw, st);
     if (s != FCHI2_OK) return s;
     int64_t max_n = 0;
@@ -536,11 +640,15 @@ fchi2_status_t fchi2_backward(fchi2_plan_t plan, const double* t, const double* 
       const int64_t n = plan->offsets[c + 1] - plan->offsets[c];
       max_n = n > max_n ? n : max_n;
     }
+    PROF_BEGIN(FCHI2_PROF_BWD_GATHER);
     e = launch_gather(plan->fp64, t, mom, plan->g, c0, nw, gA, gq, gp, max_n, st);
     if (e != hipSuccess) return hip_fail(e, "gather");
+    PROF_END();
+    PROF_BEGIN(FCHI2_PROF_BWD_FINAL);
     e = launch_finalize(x, sigma, mom, plan->g, c0, nw, dw, plan->blocks_per_curve, gq, gp,
                         grad_x, grad_sigma, st);
     if (e != hipSuccess) return hip_fail(e, "finalize");
+    PROF_END();
   }
   return FCHI2_OK;
 }
@@ -570,13 +678,172 @@ fchi2_status_t fchi2_top_peaks(fchi2_plan_t plan, const void* dchi2, int32_t hro
   return FCHI2_OK;
 }
 
+fchi2_status_t fchi2_profile(fchi2_plan_t plan, int32_t enable) {
+  g_err.clear();
+  if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
+  plan->prof = enable != 0;
+  plan->ev_used = 0;
+  plan->ev_stage.clear();
+  for (int i = 0; i < FCHI2_PROF_STAGES; ++i) {
+    plan->prof_ms[i] = 0.0;
+    plan->prof_n[i] = 0;
+  }
+  return FCHI2_OK;
+}
+
+fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* launches) {
+  g_err.clear();
+  if (!plan || !total_ms || !launches) return fail(FCHI2_ERR_ARG, "NULL argument");
+  for (size_t i = 0; i < plan->ev_stage.size(); ++i) {
+    hipEvent_t a = plan->ev_pool[2 * i], b = plan->ev_pool[2 * i + 1];
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    plan->prof_ms[plan->ev_stage[i]] += ms;
+    plan->prof_n[plan->ev_stage[i]] += 1;
+  }
+  plan->ev_used = 0;
+  plan->ev_stage.clear();
+  for (int i = 0; i < FCHI2_PROF_STAGES; ++i) {
+    total_ms[i] = plan->prof_ms[i];
+    launches[i] = plan->prof_n[i];
+  }
+  return FCHI2_OK;
+}
+
+fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* x,
+                              const double* sigma, void* workspace, size_t workspace_bytes,
+                              void* dchi2, const char* cache_path, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
+  if (!t || !x || !sigma || !dchi2) return fail(FCHI2_ERR_ARG, "NULL pointer argument");
+  fchi2_status_t s = check_ws(plan, workspace, workspace_bytes);
+  if (s != FCHI2_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  fchi2_plan_s* pl = plan;
+  int lg_nc = 0, lg_n = 0;
+  while ((1 << lg_nc) < pl->desc.n_curves) ++lg_nc;
+  while (((int64_t)1 << lg_n) < pl->max_n) ++lg_n;
+  char key[160];
+  snprintf(key, sizeof key, "gfx950 H=%d nf=%lld prec=%d w=%d curves=2^%d maxn=2^%d wavemax=%d",
+           pl->g.H, (long long)pl->g.n_freq, pl->fp64 ? 0 : 1, pl->g.w, lg_nc, lg_n,
+           pl->wave_max);
+  const std::vector<FftPlan> splits = fft_splits(pl->fp.logL, fft_tile_log());
+  auto apply = [&](const int* ln, int np, int tile, int wave) -> bool {
+    for (const FftPlan& f : splits) {
+      if (f.np != np) continue;
+      bool same = true;
+      for (int q = 1; q <= np; ++q) same = same && f.logn[q] == ln[q];
+      if (!same) continue;
+      pl->log_tile = tile;
+      pl->wave = wave;
+      apply_fft_plan(pl, f);
+      return true;
+    }
+    return false;
+  };
+  if (pl->gexec) {
+    (void)hipGraphExecDestroy(pl->gexec);
+    pl->gexec = nullptr;
+  }
+  // Cached choice?
+  if (cache_path) {
+    if (FILE* fh = fopen(cache_path, "r")) {
+      char line[512];
+      bool found = false;
+      while (!found && fgets(line, sizeof line, fh)) {
+        const char* tag = strstr(line, " | ");
+        if (!tag || strncmp(line, key, strlen(key)) != 0 || line + strlen(key) != tag) continue;
+        int np = 0, ln[kMaxPasses + 1] = {0}, tile = 0, wave = 0;
+        if (sscanf(tag, " | np=%d fft=%d,%d,%d,%d tile=%d wave=%d", &np, &ln[1], &ln[2], &ln[3],
+                   &ln[4], &tile, &wave) == 7 &&
+            (tile == 10 || tile == 11) && wave >= 1 && wave <= pl->wave_max)
+          found = apply(ln, np, tile, wave);
+      }
+      fclose(fh);
+      if (found) return FCHI2_OK;
+    }
+  }
+  // Time every candidate on the caller's data.
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const bool prof = pl->prof;
+  pl->prof = false;
+  std::vector<int> waves = {pl->wave_max};
+  for (int w = pl->wave_max / 2; w >= 1 && waves.size() < 3 && pl->desc.n_curves > 1; w /= 2)
+    waves.push_back(w);
+  float best_ms = 1e30f;
+  FftPlan best_f = pl->fp;
+  int best_tile = pl->log_tile, best_wave = pl->wave;
+  fchi2_status_t res = FCHI2_OK;
+  for (const FftPlan& f : splits) {
+    for (int tile : {10, 11}) {
+      for (int wave : waves) {
+        pl->log_tile = tile;
+        pl->wave = wave;
+        apply_fft_plan(pl, f);
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3 && res == FCHI2_OK; ++rep) {
+          hipError_t e = hipEventRecord(e0, st);
+          if (e == hipSuccess) {
+            res = enqueue_search(pl, 0, pl->desc.n_curves, t, x, sigma, (char*)workspace, dchi2,
+                                 nullptr, nullptr, st);
+          }
+          if (e == hipSuccess && res == FCHI2_OK) e = hipEventRecord(e1, st);
+          if (e == hipSuccess && res == FCHI2_OK) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess && res == FCHI2_OK) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) res = hip_fail(e, "autotune timing");
+          if (rep > 0 && ms < ms_min) ms_min = ms;  // first run warms up
+        }
+        if (res != FCHI2_OK) break;
+        if (ms_min < best_ms) {
+          best_ms = ms_min;
+          best_f = f;
+          best_tile = tile;
+          best_wave = wave;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  pl->prof = prof;
+  pl->log_tile = best_tile;
+  pl->wave = best_wave;
+  apply_fft_plan(pl, best_f);
+  pl->last_ws = nullptr;
+  if (res != FCHI2_OK) return res;
+  if (cache_path) {
+    if (FILE* fh = fopen(cache_path, "a")) {
+      fprintf(fh, "%s | np=%d fft=%d,%d,%d,%d tile=%d wave=%d ms=%.4f\n", key, best_f.np,
+              best_f.logn[1], best_f.logn[2], best_f.logn[3], best_f.logn[4], best_tile,
+              best_wave, best_ms);
+      fclose(fh);
+    }
+  }
+  return FCHI2_OK;
+}
+
+fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n) {
+  g_err.clear();
+  if (!plan || !info || n < 8) return fail(FCHI2_ERR_ARG, "plan/info NULL or n < 8");
+  info[0] = plan->fp.np;
+  for (int q = 1; q <= kMaxPasses; ++q) info[q] = plan->fp.logn[q];
+  info[5] = plan->log_tile;
+  info[6] = plan->wave;
+  info[7] = plan->g.w;
+  return FCHI2_OK;
+}
+
 void fchi2_destroy(fchi2_plan_t plan) {
   if (!plan) return;
+  for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
   if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
   if (plan->d_off) (void)hipFree(plan->d_off);
   if (plan->d_tw_stage) (void)hipFree(plan->d_tw_stage);
-  if (plan->d_tw_lo) (void)hipFree(plan->d_tw_lo);
-  if (plan->d_tw_hi) (void)hipFree(plan->d_tw_hi);
+  if (plan->d_tw_small) (void)hipFree(plan->d_tw_small);
   if (plan->d_D) hipFree(plan->d_D);
   if (plan->d_gl) (void)hipFree(plan->d_gl);
   delete plan;

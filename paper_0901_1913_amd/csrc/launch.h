@@ -12,31 +12,33 @@ struct FftPassArgs {
   int q;                       // digit handled by this pass (1 = least significant)
   int logn[kMaxPasses + 1];    // log2 N_d per digit d = 1..np
   int logL;
-  int tw_s;                    // split of the two-level omega_L table
   int curve0;                  // first curve of the wave
   void* zc;                    // forward: pruned spectra [wave][P][2][n_freq]
   void* grid_out;              // adjoint: natural-order grid output
 };
 
-// Moments, validity flags and chi2_0 of every curve (one workgroup per curve).
+// Moments, validity flags and chi2_0 of every curve: bpc workgroups per
+// curve reduce chunks into part[n_curves][bpc], then one pass combines them.
 hipError_t launch_moments(const double* t, const double* x, const double* sigma,
-                          const int64_t* offsets, int n_curves, const Geom& g, Moments* mom,
-                          double* chi2_0, hipStream_t st);
+                          const int64_t* offsets, int n_curves, int bpc, const Geom& g,
+                          MomPart* part, Moments* mom, double* chi2_0, hipStream_t st);
 
 // Spread w and w*(x - xbar) of each curve of the wave onto its P packed grids.
 hipError_t launch_spread(bool fp64, const double* t, const double* x, const double* sigma,
                          const Moments* mom, const Geom& g, int curve0, int n_curves,
                          void* grid, int log_tile, hipStream_t st);
 
-int fft_tile_log(bool fp64);
+// log2 of the elements of one FFT tile (rows x columns held in LDS).
+int fft_tile_log();
+// tws: omega_{2^13}^e (FP64), twsm: omega_L^e for e < 2^fft_tile_log() (FP64).
 hipError_t launch_fft_pass(bool fp64, const FftPassArgs& a, int logn, int logt, const void* in,
                            void* out, const Moments* mom, const Geom& g, const void* tws,
-                           const void* twl, const void* twh, int n_curves, int64_t ncols,
-                           hipStream_t st);
+                           const void* twsm, int n_curves, int64_t ncols, hipStream_t st);
 
 // Deconvolution / origin-shift factors D[k] = exp(-2 pi i k c_off / L) / phi_hat(k).
-hipError_t launch_deconv_init(bool fp64, void* D, const Geom& g, const double* gl_x,
-                              const double* gl_w, int n_gl, hipStream_t st);
+// FP64 complex [n_freq].
+hipError_t launch_deconv_init(void* D, const Geom& g, const double* gl_x, const double* gl_w,
+                              int n_gl, hipStream_t st);
 
 // Normal-matrix assembly, Cholesky and prefix Delta chi2 per bin.
 hipError_t launch_solve(bool fp64, const void* zc, const void* D, const Moments* mom,

@@ -35,7 +35,7 @@ struct Layout {
 // already multiplied by the deconvolution / origin-shift factor D[k].
 template <int H, typename R>
 __device__ __forceinline__ void load_spectra(const cplx<R>* __restrict__ zc, int64_t nf,
-                                             int64_t base_pair, int64_t k, cplx<R> Dk_,
+                                             int64_t base_pair, int64_t k, cplx<double> Dk_,
                                              double W, double* Qr, double* Qi, double* Pr,
                                              double* Pi) {
   constexpr int P = Layout<H>::P;
@@ -106,7 +106,7 @@ __device__ __forceinline__ O nan_of() {
 
 template <int H, typename R, typename O>
 __global__ __launch_bounds__(kNT) void k_solve(const cplx<R>* __restrict__ zc,
-                                               const cplx<R>* __restrict__ D,
+                                               const cplx<double>* __restrict__ D,
                                                const Moments* __restrict__ mom, Geom g,
                                                int curve0, double eps, O* __restrict__ out,
                                                uint8_t* __restrict__ flags) {
@@ -185,7 +185,7 @@ hipError_t solve_h(bool fp64, const void* zc, const void* D, const Moments* mom,
                        (double*)out, flags);
   else
     hipLaunchKernelGGL((k_solve<H, float, float>), gr, dim3(kNT), 0, st, (const cplx<float>*)zc,
-                       (const cplx<float>*)D, mom, g, curve0, eps, (float*)out, flags);
+                       (const cplx<double>*)D, mom, g, curve0, eps, (float*)out, flags);
   return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@
 //
 // Two real grids are packed per complex grid (real part, imaginary part);
 // each workgroup owns a tile of cells of one packed grid and sums the kernel
-// contributions of its points cell by cell (deterministic, no atomics).
+// contributions of its points cell by cell (deterministic, no atomics).  The
+// arithmetic is FP64; the grid is stored as S (float for mixed plans).
 #include <cmath>
 
 #include "fchi2_internal.h"
@@ -42,24 +43,28 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
   return r;
 }
 
-__global__ __launch_bounds__(kNT) void k_moments(const double* __restrict__ t,
-                                                 const double* __restrict__ x,
-                                                 const double* __restrict__ sigma,
-                                                 const int64_t* __restrict__ off, Geom g,
-                                                 Moments* __restrict__ mom,
-                                                 double* __restrict__ chi2_out) {
+// Phase 1: block b of curve c reduces a contiguous chunk of the curve to
+// (W_b, mean_b, M2_b = sum w (x - mean_b)^2) and validity bits.
+__global__ __launch_bounds__(kNT) void k_moments_part(const double* __restrict__ t,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ sigma,
+                                                      const int64_t* __restrict__ off,
+                                                      int bpc, MomPart* __restrict__ part) {
   __shared__ double red[kNT];
   __shared__ uint32_t bad_s;
-  const int c = blockIdx.x;
+  const int c = blockIdx.y;
+  const int b = blockIdx.x;
   const int tid = threadIdx.x;
-  const int64_t a = off[c], b = off[c + 1];
-  const int64_t n = b - a;
+  const int64_t a = off[c], e = off[c + 1];
+  const int64_t n = e - a;
+  const int64_t chunk = (n + bpc - 1) / bpc;
+  const int64_t lo = a + (int64_t)b * chunk;
+  const int64_t hi = (lo + chunk < e) ? lo + chunk : e;
   if (tid == 0) bad_s = 0;
   __syncthreads();
-
   double sw = 0.0, swx = 0.0;
   uint32_t bad = 0;
-  for (int64_t i = a + tid; i < b; i += kNT) {
+  for (int64_t i = lo + tid; i < hi; i += kNT) {
     const double ti = t[i], xi = x[i], si = sigma[i];
     if (!isfinite(ti) || !isfinite(xi) || !isfinite(si) || !(si > 0.0)) bad |= CF_NONFINITE;
     if (i > a && !(ti >= t[i - 1])) bad |= CF_UNSORTED;
@@ -70,42 +75,73 @@ __global__ __launch_bounds__(kNT) void k_moments(const double* __restrict__ t,
   if (bad) atomicOr(&bad_s, bad);
   const double W = block_sum(sw, red);
   const double WX = block_sum(swx, red);
-  const double xbar = WX / W;
+  const double mean = (W > 0.0) ? WX / W : 0.0;
   double sc = 0.0;
-  for (int64_t i = a + tid; i < b; i += kNT) {
+  for (int64_t i = lo + tid; i < hi; i += kNT) {
     const double si = sigma[i];
-    const double w = 1.0 / (si * si);
-    const double y = x[i] - xbar;
-    sc += w * y * y;
+    const double y = x[i] - mean;
+    sc += y * y / (si * si);
   }
-  const double chi2_0 = block_sum(sc, red);
+  const double M2 = block_sum(sc, red);
   if (tid == 0) {
-    Moments m;
-    m.W = W;
-    m.xbar = xbar;
-    m.chi2_0 = chi2_0;
-    m.start = a;
-    m.n = n;
-    uint32_t fl = bad_s;
-    if (n <= 0) {
-      fl |= CF_EMPTY;
-      m.T0 = 0.0;
-      m.span = 0.0;
-    } else {
-      m.T0 = t[a];
-      m.span = t[b - 1] - t[a];
-    }
-    if (n < 2 * g.H + 1) fl |= CF_FEW;
-    if (!(fl & kCurveFatal)) {
-      const double v = m.span * g.df;
-      const double pos = ((double)(2 * g.H) * v) * (double)g.L + (double)g.c_off;
-      if (!(pos + (double)(g.w / 2) + 3.0 <= (double)g.L)) fl |= CF_WRAP;
-    }
-    m.flags = fl;
-    m.pad = 0;
-    mom[c] = m;
-    if (chi2_out) chi2_out[c] = (fl & kCurveFatal) ? NAN : chi2_0;
+    MomPart pp;
+    pp.W = W;
+    pp.mean = mean;
+    pp.M2 = M2;
+    pp.bad = bad_s;
+    pp.pad = 0;
+    part[(int64_t)c * bpc + b] = pp;
   }
+}
+
+// Phase 2: one thread per curve combines the chunks in order (parallel
+// variance update) and writes the curve's Moments and chi2_0.
+__global__ __launch_bounds__(kNT) void k_moments_fin(const double* __restrict__ t,
+                                                     const int64_t* __restrict__ off,
+                                                     int n_curves, int bpc,
+                                                     const MomPart* __restrict__ part, Geom g,
+                                                     Moments* __restrict__ mom,
+                                                     double* __restrict__ chi2_out) {
+  const int c = blockIdx.x * kNT + threadIdx.x;
+  if (c >= n_curves) return;
+  const int64_t a = off[c], e = off[c + 1];
+  const int64_t n = e - a;
+  double W = 0.0, mean = 0.0, M2 = 0.0;
+  uint32_t fl = 0;
+  for (int b = 0; b < bpc; ++b) {
+    const MomPart pp = part[(int64_t)c * bpc + b];
+    fl |= pp.bad;
+    if (!(pp.W > 0.0)) continue;
+    const double Wn = W + pp.W;
+    const double dlt = pp.mean - mean;
+    mean += dlt * (pp.W / Wn);
+    M2 += pp.M2 + dlt * dlt * (W * pp.W / Wn);
+    W = Wn;
+  }
+  Moments m;
+  m.W = W;
+  m.xbar = mean;
+  m.chi2_0 = M2;
+  m.start = a;
+  m.n = n;
+  if (n <= 0) {
+    fl |= CF_EMPTY;
+    m.T0 = 0.0;
+    m.span = 0.0;
+  } else {
+    m.T0 = t[a];
+    m.span = t[e - 1] - t[a];
+  }
+  if (n < 2 * g.H + 1) fl |= CF_FEW;
+  if (!(fl & kCurveFatal)) {
+    const double v = m.span * g.df;
+    const double pos = ((double)(2 * g.H) * v) * (double)g.L + (double)g.c_off;
+    if (!(pos + (double)(g.w / 2) + 3.0 <= (double)g.L)) fl |= CF_WRAP;
+  }
+  m.flags = fl;
+  m.pad = 0;
+  mom[c] = m;
+  if (chi2_out) chi2_out[c] = (fl & kCurveFatal) ? NAN : M2;
 }
 
 // Cell coordinate of point i for harmonic multiple m (FP64 phase reduction).
@@ -136,31 +172,39 @@ __device__ int64_t wave_lower_bound(const double* __restrict__ t, int64_t lo, in
   return lo + __popcll(__ballot(lt));
 }
 
-template <typename R>
-__device__ __forceinline__ R es_kernel(R z, R beta) {
-  // exp(beta * (sqrt(1 - z^2) - 1)) on |z| < 1, else 0.
-  const R q = (R)1 - z * z;
-  if (!(q > (R)0)) return (R)0;
-  if constexpr (sizeof(R) == 4) {
-    return expf(beta * (sqrtf(q) - 1.0f));
+// Exponential-of-semicircle kernel exp(beta (sqrt(1 - z^2) - 1)) on |z| < 1.
+// The argument is formed in FP64.  With EXACT the exponential is FP64 too;
+// otherwise the FP32 exponential of the rounded argument is corrected by the
+// rounding residual, exp(a + r) = exp(a) (1 + r + O(r^2)), which keeps the
+// kernel value within about one FP32 ulp although the argument reaches -2.3 w.
+template <bool EXACT>
+__device__ __forceinline__ double es_kernel(double z, double beta) {
+  const double q = 1.0 - z * z;
+  if (!(q > 0.0)) return 0.0;
+  const double arg = beta * (sqrt(q) - 1.0);
+  if constexpr (EXACT) {
+    return exp(arg);
   } else {
-    return exp(beta * (sqrt(q) - 1.0));
+    const float a = (float)arg;
+    const double r = arg - (double)a;
+    return (double)expf(a) * (1.0 + r);
   }
 }
 
-template <typename R, int LOGB>
+template <typename S, int LOGB>
 __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ sigma,
                                                 const Moments* __restrict__ mom, Geom g,
-                                                int curve0, cplx<R>* __restrict__ grid) {
+                                                int curve0, cplx<S>* __restrict__ grid) {
+  constexpr bool EXACT = sizeof(S) == 8;
   constexpr int B = 1 << LOGB;
   constexpr int CPT = B / kNT;
   constexpr int CH = 1024;
   __shared__ int s_j0[CH];
-  __shared__ R s_fr[CH];
-  __shared__ R s_re[CH];
-  __shared__ R s_im[CH];
+  __shared__ double s_fr[CH];
+  __shared__ double s_re[CH];
+  __shared__ double s_im[CH];
   __shared__ int64_t s_rng[2];
 
   const int tid = threadIdx.x;
@@ -173,17 +217,17 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
   if (a0 >= E) return;
 
   const int hw = g.w / 2;
-  const R two_over_w = (R)(2.0 / (double)g.w);
-  const R beta = (R)g.beta;
+  const double two_over_w = 2.0 / (double)g.w;
+  const double beta = g.beta;
   const double Ld = (double)g.L;
   const double coff = (double)g.c_off;
   const int64_t pa = mo.start, pb = mo.start + mo.n;
 
-  R acc_re[CPT], acc_im[CPT];
+  double acc_re[CPT], acc_im[CPT];
 #pragma unroll
   for (int u = 0; u < CPT; ++u) {
-    acc_re[u] = (R)0;
-    acc_im[u] = (R)0;
+    acc_re[u] = 0.0;
+    acc_im[u] = 0.0;
   }
 
   for (int comp = 0; comp < 2; ++comp) {
@@ -223,9 +267,9 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
           sim = sa;
         }
         s_j0[q] = (int)((int64_t)fl - a0);
-        s_fr[q] = (R)(pos - fl);
-        s_re[q] = (R)sre;
-        s_im[q] = (R)sim;
+        s_fr[q] = pos - fl;
+        s_re[q] = sre;
+        s_im[q] = sim;
       }
       __syncthreads();
 #pragma unroll
@@ -239,12 +283,12 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
           if (s_j0[mid] < key) lo = mid + 1;
           else hi = mid;
         }
-        R ar = acc_re[u], ai = acc_im[u];
+        double ar = acc_re[u], ai = acc_im[u];
         for (int q = lo; q < cnt; ++q) {
           const int j0 = s_j0[q];
           if (j0 > jl + hw) break;
-          const R d = (R)(jl - j0) - s_fr[q];
-          const R phi = es_kernel<R>(d * two_over_w, beta);
+          const double d = (double)(jl - j0) - s_fr[q];
+          const double phi = es_kernel<EXACT>(d * two_over_w, beta);
           ar += phi * s_re[q];
           ai += phi * s_im[q];
         }
@@ -255,13 +299,12 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
     }
   }
 
-  cplx<R>* out = grid + ((int64_t)cw * g.P + p) * g.L + a0;
+  cplx<S>* out = grid + ((int64_t)cw * g.P + p) * g.L + a0;
 #pragma unroll
-  for (int u = 0; u < CPT; ++u) out[tid + u * kNT] = cmk<R>(acc_re[u], acc_im[u]);
+  for (int u = 0; u < CPT; ++u) out[tid + u * kNT] = cmk<S>((S)acc_re[u], (S)acc_im[u]);
 }
 
-template <typename R>
-__global__ __launch_bounds__(kNT) void k_deconv(cplx<R>* __restrict__ D, Geom g,
+__global__ __launch_bounds__(kNT) void k_deconv(cplx<double>* __restrict__ D, Geom g,
                                                 const double* __restrict__ gx,
                                                 const double* __restrict__ gw, int ng) {
   const int64_t k = (int64_t)blockIdx.x * kNT + threadIdx.x;
@@ -275,16 +318,20 @@ __global__ __launch_bounds__(kNT) void k_deconv(cplx<R>* __restrict__ D, Geom g,
   const double ang = -2.0 * (double)e / (double)g.L;
   double sn, cs;
   sincospi(ang, &sn, &cs);
-  D[k] = cmk<R>((R)(cs / s), (R)(sn / s));
+  D[k] = cmk<double>(cs / s, sn / s);
 }
 
 }  // namespace
 
 hipError_t launch_moments(const double* t, const double* x, const double* sigma,
-                          const int64_t* offsets, int n_curves, const Geom& g, Moments* mom,
-                          double* chi2_0, hipStream_t st) {
-  hipLaunchKernelGGL(k_moments, dim3(n_curves), dim3(kNT), 0, st, t, x, sigma, offsets, g, mom,
-                     chi2_0);
+                          const int64_t* offsets, int n_curves, int bpc, const Geom& g,
+                          MomPart* part, Moments* mom, double* chi2_0, hipStream_t st) {
+  hipLaunchKernelGGL(k_moments_part, dim3(bpc, n_curves), dim3(kNT), 0, st, t, x, sigma,
+                     offsets, bpc, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_moments_fin, dim3((n_curves + kNT - 1) / kNT), dim3(kNT), 0, st, t,
+                     offsets, n_curves, bpc, part, g, mom, chi2_0);
   return hipGetLastError();
 }
 
@@ -313,15 +360,10 @@ hipError_t launch_spread(bool fp64, const double* t, const double* x, const doub
   return hipGetLastError();
 }
 
-hipError_t launch_deconv_init(bool fp64, void* D, const Geom& g, const double* gl_x,
-                              const double* gl_w, int n_gl, hipStream_t st) {
+hipError_t launch_deconv_init(void* D, const Geom& g, const double* gl_x, const double* gl_w,
+                              int n_gl, hipStream_t st) {
   const unsigned nb = (unsigned)((g.n_freq + kNT - 1) / kNT);
-  if (fp64)
-    hipLaunchKernelGGL((k_deconv<double>), dim3(nb), dim3(kNT), 0, st, (cplx<double>*)D, g,
-                       gl_x, gl_w, n_gl);
-  else
-    hipLaunchKernelGGL((k_deconv<float>), dim3(nb), dim3(kNT), 0, st, (cplx<float>*)D, g, gl_x,
-                       gl_w, n_gl);
+  hipLaunchKernelGGL(k_deconv, dim3(nb), dim3(kNT), 0, st, (cplx<double>*)D, g, gl_x, gl_w, n_gl);
   return hipGetLastError();
 }
 

@@ -26,9 +26,13 @@ CURVE_NONFINITE, CURVE_UNSORTED, CURVE_WRAP, CURVE_FEW, CURVE_EMPTY = 8, 16, 32,
 
 EXPORTS = (
     "fchi2_plan", "fchi2_workspace_bytes", "fchi2_total_points", "fchi2_search",
+    "fchi2_search_curves",
     "fchi2_backward", "fchi2_top_peaks_scratch_bytes", "fchi2_top_peaks",
-    "fchi2_destroy", "fchi2_status_string", "fchi2_last_error",
+    "fchi2_destroy", "fchi2_status_string", "fchi2_last_error", "fchi2_profile",
+    "fchi2_profile_read", "fchi2_autotune", "fchi2_plan_info",
 )
+PROF_STAGES = ("moments", "spread", "fft_first", "fft_mid", "fft_last", "solve",
+               "bwd_solve", "bwd_fft", "bwd_gather", "bwd_final")
 
 
 class PlanDesc(ctypes.Structure):
@@ -72,6 +76,8 @@ def lib() -> ctypes.CDLL:
     L.fchi2_total_points.restype = i64
     L.fchi2_search.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp, vp]
     L.fchi2_search.restype = ctypes.c_int
+    L.fchi2_search_curves.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp, vp, vp, vp]
+    L.fchi2_search_curves.restype = ctypes.c_int
     L.fchi2_backward.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
     L.fchi2_backward.restype = ctypes.c_int
     L.fchi2_top_peaks_scratch_bytes.argtypes = [vp, i32]
@@ -84,6 +90,15 @@ def lib() -> ctypes.CDLL:
     L.fchi2_status_string.restype = ctypes.c_char_p
     L.fchi2_last_error.argtypes = []
     L.fchi2_last_error.restype = ctypes.c_char_p
+    L.fchi2_profile.argtypes = [vp, i32]
+    L.fchi2_profile.restype = ctypes.c_int
+    L.fchi2_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64)]
+    L.fchi2_profile_read.restype = ctypes.c_int
+    L.fchi2_autotune.argtypes = [vp, vp, vp, vp, vp, sz, vp, ctypes.c_char_p, vp]
+    L.fchi2_autotune.restype = ctypes.c_int
+    L.fchi2_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), i32]
+    L.fchi2_plan_info.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -195,6 +210,23 @@ class Plan:
             ctypes.c_void_p(_stream_handle(stream))))
         return dchi2, chi2_0, flags
 
+    def search_curves(self, first: int, count: int, t, x, sigma, dchi2, chi2_0, flags=None,
+                      workspace=None, stream=None):
+        """fchi2_search on curves [first, first + count) into full-size outputs."""
+        torch = _torch()
+        f64 = torch.float64
+        ws = self.workspace(t.device) if workspace is None else workspace
+        _check(lib().fchi2_search_curves(
+            self._h, int(first), int(count), _dev_ptr(t, f64, self.n_total, "t"),
+            _dev_ptr(x, f64, self.n_total, "x"), _dev_ptr(sigma, f64, self.n_total, "sigma"),
+            ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+            _dev_ptr(dchi2, self.out_dtype, self.n_curves * self.H * self.n_freq, "dchi2"),
+            _dev_ptr(chi2_0, f64, self.n_curves, "chi2_0"),
+            _dev_ptr(flags, torch.uint8, self.n_curves * self.n_freq, "flags")
+            if flags is not None else ctypes.c_void_p(0),
+            ctypes.c_void_p(_stream_handle(stream))))
+        return dchi2, chi2_0, flags
+
     def backward(self, t, x, sigma, grad_dchi2, grad_x=None, grad_sigma=None,
                  workspace=None, stream=None):
         """dLoss/dx and dLoss/dsigma given dLoss/dDelta chi2 (same layout as dchi2)."""
@@ -230,6 +262,43 @@ class Plan:
             _dev_ptr(out, torch.int64, self.n_curves * K, "out"),
             ctypes.c_void_p(_stream_handle(stream))))
         return out
+
+    def autotune(self, t, x, sigma, cache_path: Optional[str] = None, workspace=None,
+                 stream=None):
+        """Time the candidate schedules on these inputs and keep the fastest."""
+        torch = _torch()
+        f64 = torch.float64
+        ws = self.workspace(t.device) if workspace is None else workspace
+        scratch = torch.empty((self.n_curves, self.H, self.n_freq), dtype=self.out_dtype,
+                              device=t.device)
+        _check(lib().fchi2_autotune(
+            self._h, _dev_ptr(t, f64, self.n_total, "t"), _dev_ptr(x, f64, self.n_total, "x"),
+            _dev_ptr(sigma, f64, self.n_total, "sigma"), ctypes.c_void_p(ws.data_ptr()),
+            ctypes.c_size_t(ws.numel()), ctypes.c_void_p(scratch.data_ptr()),
+            cache_path.encode() if cache_path else None,
+            ctypes.c_void_p(_stream_handle(stream))))
+        return self.info()
+
+    def info(self) -> dict:
+        """The plan's schedule: FFT radices, spreading tile, wave, kernel width."""
+        arr = (ctypes.c_int32 * 8)()
+        _check(lib().fchi2_plan_info(self._h, arr, 8))
+        np_ = int(arr[0])
+        return {"fft_log_radices": [int(arr[q]) for q in range(1, np_ + 1)],
+                "spread_tile": 1 << int(arr[5]), "curves_per_wave": int(arr[6]),
+                "kernel_width": int(arr[7])}
+
+    def profile(self, enable: bool = True):
+        """Start (or stop) recording HIP event pairs around every launch."""
+        _check(lib().fchi2_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{stage: (total_ms, launches)} accumulated since profile() (waits for events)."""
+        n = len(PROF_STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(lib().fchi2_profile_read(self._h, ms, cnt))
+        return {PROF_STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
 
     def close(self):
         if getattr(self, "_h", None):

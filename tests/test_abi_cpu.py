@@ -72,6 +72,12 @@ def test_null_arguments():
     assert L.fchi2_search(None, None, None, None, None, 0, None, None, None, None) == F.ERR_ARG
     assert L.fchi2_backward(None, None, None, None, None, None, 0, None, None, None) == F.ERR_ARG
     assert L.fchi2_top_peaks(None, None, 0, 1, 1, None, 0, None, None) == F.ERR_ARG
+    assert L.fchi2_search_curves(None, 0, 1, None, None, None, None, 0, None, None, None,
+                                 None) == F.ERR_ARG
+    assert L.fchi2_autotune(None, None, None, None, None, 0, None, None, None) == F.ERR_ARG
+    assert L.fchi2_plan_info(None, None, 8) == F.ERR_ARG
+    assert L.fchi2_profile(None, 1) == F.ERR_ARG
+    assert L.fchi2_profile_read(None, None, None) == F.ERR_ARG
     assert L.fchi2_workspace_bytes(None) == 0
     assert L.fchi2_top_peaks_scratch_bytes(None, 4) == 0
     L.fchi2_destroy(None)
