@@ -29,6 +29,29 @@ METRIC = ("trial freqs·H/sec for Δχ² (rel err ≤1e-5 vs FP64 oracle); "
           "batched vs plain")
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed PMC summary, per stage, or None
+    for a stage whose kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{workload}_mixed_hbm_traffic.md")
+    if not os.path.exists(path):
+        return {}
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return {}
+    meta = json.loads(m.group(1))
+    src = {"fft_first": "fft.hip", "fft_mid": "fft.hip", "fft_last": "fft.hip",
+           "solve": "solve.hip", "spread": "spread.hip"}
+    out = {}
+    for st, nbytes in meta.get("bytes_per_launch", {}).items():
+        f = os.path.join(ROOT, "paper_0901_1913_amd", "csrc", src.get(st, ""))
+        ok = os.path.isfile(f) and (hashlib.sha256(open(f, "rb").read()).hexdigest()[:16]
+                                    == meta.get("source_sha256_16", {}).get(st))
+        out[st] = int(nbytes) if ok else None
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -157,6 +180,9 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-survey vs plain-loop comparison")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run one device copy of this many MiB (a known-size kernel "
+                         "against which HBM counters are scaled)")
     a = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -187,6 +213,15 @@ def main(argv=None):
     flags = torch.empty((1, cur.n_freq), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
 
+    if a.calib_copy_mb > 0:
+        nel = a.calib_copy_mb * (1 << 20) // 4
+        c_src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        c_dst = torch.empty_like(c_src)
+        torch.cuda.synchronize()
+        c_dst.copy_(c_src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {a.calib_copy_mb} MiB read + {a.calib_copy_mb} MiB written")
+        del c_src, c_dst
     for _ in range(a.warmup):
         plan.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, flags=flags, workspace=ws)
     torch.cuda.synchronize()
@@ -222,7 +257,9 @@ def main(argv=None):
     achieved = nbytes[dom] / (dom_ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "bytes_per_launch": int(nbytes[dom]),
+            "traffic": (measured_traffic(a.workload).get(dom)
+                        if cur.precision == "mixed" else None),
+            "bytes_per_launch": int(nbytes[dom]),
             "avg_launch_ms": round(dom_ms, 5)}
     stage_gbs = {k: round(nbytes[k] / (v[0] * 1e-3) / 1e9, 1) for k, v in st_avg.items()
                  if k in nbytes and v[0] > 0}

@@ -117,6 +117,29 @@ constexpr int kLE = 12;   // log2 of the tile: 4096 complex elements
 constexpr int kEPT = (1 << kLE) / kNT;  // elements per thread (16)
 using C = cplx<double>;
 
+// Grid data each pass touches once.  Runs of at least 128 bytes (NT) are
+// loaded and stored non-temporally (streaming); shorter runs measured slower
+// that way and use ordinary accesses.
+template <bool NT, typename S>
+__device__ __forceinline__ cplx<S> ntl(const cplx<S>* p) {
+  if constexpr (NT) {
+    cplx<S> r;
+    r.x = __builtin_nontemporal_load(&p->x);
+    r.y = __builtin_nontemporal_load(&p->y);
+    return r;
+  } else {
+    return *p;
+  }
+}
+template <bool NT, typename S>
+__device__ __forceinline__ void nts(cplx<S>* p, cplx<S> v) {
+  if constexpr (NT) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+  } else {
+    *p = v;
+  }
+}
 template <typename S>
 __device__ __forceinline__ C widen(cplx<S> v) {
   return cmk<double>((double)v.x, (double)v.y);
@@ -227,6 +250,7 @@ __global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<S>* 
   constexpr int T = 1 << LOGT;
   constexpr int PT = (T == 1) ? 1 : T + 1;
   static_assert(N * T == (1 << kLE), "tile size");
+  constexpr bool NT = T * sizeof(cplx<S>) >= 128;
   using S0 = Stage<LOGN, LOGT, 0>;
   using SL = Stage<LOGN, LOGT, last_logns(LOGN)>;
   __shared__ cplx<S> sm[N * PT];
@@ -269,7 +293,7 @@ __global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<S>* 
       for (int i = 0; i < S0::RAD; ++i) {
         const int r = S0::in_row(b, i);
         C val = cmk<double>(0.0, 0.0);
-        if (r < r_skip_lo || r >= r_skip_hi) val = widen(src[g0 + cc + Sd * r]);
+        if (r < r_skip_lo || r >= r_skip_hi) val = widen(ntl<NT>(&src[g0 + cc + Sd * r]));
         v[it * S0::RAD + i] = val;
       }
     }
@@ -298,7 +322,7 @@ __global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<S>* 
       const int cc = S0::col(tid, it), b = S0::bfly(tid, it);
 #pragma unroll
       for (int i = 0; i < S0::RAD; ++i)
-        v[it * S0::RAD + i] = widen(base[(int64_t)S0::in_row(b, i) * Tail + cc]);
+        v[it * S0::RAD + i] = widen(ntl<NT>(&base[(int64_t)S0::in_row(b, i) * Tail + cc]));
     }
     if (a.kind == PASS_MID) {
       const int64_t jd = pre & (((int64_t)1 << a.logn[a.q - 1]) - 1);
@@ -344,7 +368,7 @@ __global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<S>* 
         rest >>= a.logn[d];
         rev = (rev << a.logn[d]) | dig;
       }
-      dst[rev * N + k] = sm[k * PT + cc];
+      nts<NT>(&dst[rev * N + k], sm[k * PT + cc]);
     }
   } else if (a.kind == PASS_MID) {
     const int64_t Tail = L >> (low_bits + LOGN);
@@ -358,7 +382,7 @@ __global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<S>* 
 #pragma unroll
       for (int i = 0; i < SL::RAD; ++i) {
         const int k = SL::out_row(b, i);
-        base[(int64_t)k * Tail + cc] = narrow<S>(cmul(v[it * SL::RAD + i], cmul(fc, tr[k])));
+        nts<NT>(&base[(int64_t)k * Tail + cc], narrow<S>(cmul(v[it * SL::RAD + i], cmul(fc, tr[k]))));
       }
     }
   } else {

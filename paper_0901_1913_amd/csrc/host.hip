@@ -203,6 +203,7 @@ struct fchi2_plan_s {
   // workspace layout (byte offsets)
   int mom_bpc = 1;
   size_t off_part = 0;
+  size_t off_tb = 0;
   size_t off_mom = 0, off_gA = 0, off_gB = 0, off_zc = 0, off_gq = 0, off_gp = 0, off_dw = 0;
   size_t ws_bytes = 0;
   int blocks_per_curve = 0;
@@ -318,7 +319,8 @@ fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double
     void* gB = ws + pl->off_gB;
     void* zc = ws + pl->off_zc + (keep ? (size_t)c0 * zc_curve : 0);
     PROF_BEGIN(FCHI2_PROF_SPREAD);
-    e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, gA, pl->log_tile, st);
+    e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n,
+                      (int32_t*)(ws + pl->off_tb), gA, pl->log_tile, st);
     if (e != hipSuccess) return hip_fail(e, "spread");
     PROF_END();
     fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st);
@@ -456,6 +458,9 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   off = align256(off + sizeof(Moments) * (size_t)d.n_curves);
   pl->off_part = off;
   off = align256(off + sizeof(MomPart) * (size_t)d.n_curves * pl->mom_bpc);
+  pl->off_tb = off;
+  // Sized for the smallest spreading tile the autotuner may pick.
+  off = align256(off + tile_bounds_bytes(g, 10, pl->wave));
   pl->off_gA = off;
   off = align256(off + grid_curve * pl->wave);
   pl->off_gB = off;

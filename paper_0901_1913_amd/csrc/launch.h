@@ -24,9 +24,11 @@ hipError_t launch_moments(const double* t, const double* x, const double* sigma,
                           MomPart* part, Moments* mom, double* chi2_0, hipStream_t st);
 
 // Spread w and w*(x - xbar) of each curve of the wave onto its P packed grids.
+// tb: tile -> point-range table, tile_bounds_bytes(g, log_tile, n_curves).
 hipError_t launch_spread(bool fp64, const double* t, const double* x, const double* sigma,
                          const Moments* mom, const Geom& g, int curve0, int n_curves,
-                         void* grid, int log_tile, hipStream_t st);
+                         int64_t max_n, int32_t* tb, void* grid, int log_tile, hipStream_t st);
+size_t tile_bounds_bytes(const Geom& g, int log_tile, int n_curves);
 
 // log2 of the elements of one FFT tile (rows x columns held in LDS).
 int fft_tile_log();

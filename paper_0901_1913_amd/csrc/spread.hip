@@ -151,25 +151,52 @@ __device__ __forceinline__ double cell_pos(const double* __restrict__ t, int64_t
   return ((double)m * v) * L + c_off;
 }
 
-// First index in [lo, hi) whose cell position is >= target (positions are
-// nondecreasing).  Executed by one full wavefront; 64-ary search.
-__device__ int64_t wave_lower_bound(const double* __restrict__ t, int64_t lo, int64_t hi,
-                                    double target, double T0, double df, int m, double L,
-                                    double c_off) {
-  const int lane = threadIdx.x & 63;
-  while (hi - lo > 64) {
-    const int64_t step = (hi - lo) / 64;
-    const int64_t idx = lo + step * (lane + 1) - 1;
-    const bool lt = cell_pos(t, idx, T0, df, m, L, c_off) < target;
-    const int cnt = __popcll(__ballot(lt));
-    const int64_t nlo = lo + step * cnt;
-    const int64_t nhi = (cnt == 64) ? hi : lo + step * (cnt + 1);
-    lo = nlo;
-    hi = nhi;
+// Tile -> point-range table.  For harmonic m and tile t of B cells, the
+// points a tile may need are those with position in
+// [x_t, x_{t+2}), x_t = t B - w/2 - 2 (a superset of the kernel footprint).
+// tb[t] = first point index i (relative to the curve) with pos_i >= x_t.  The
+// intervals (pos_{i-1}, pos_i] partition the line, so thread i writes exactly
+// the entries whose x_t falls in its interval: one scatter, no searches.
+// Entries stop at tile_limit(): tiles past it hold no point of harmonic m.
+// Last table entry written for harmonic m: the tile after the one holding the
+// last point's footprint, plus the two-tile lookahead of the spreading.
+__device__ __forceinline__ int64_t tile_limit(const double* __restrict__ t, const Moments& mo,
+                                              const Geom& g, int m, int log_tile) {
+  const double last = cell_pos(t, mo.start + mo.n - 1, mo.T0, g.df, m, (double)g.L,
+                               (double)g.c_off);
+  return (int64_t)floor((last + (double)(g.w / 2 + 2)) / (double)((int64_t)1 << log_tile)) + 3;
+}
+
+__global__ __launch_bounds__(kNT) void k_tile_bounds(const double* __restrict__ t,
+                                                     const Moments* __restrict__ mom, Geom g,
+                                                     int curve0, int log_tile, int ntb,
+                                                     int32_t* __restrict__ tb) {
+  const int cw = blockIdx.z;
+  const int m = blockIdx.y + 1;
+  const Moments mo = mom[curve0 + cw];
+  if (mo.flags & kCurveFatal) return;
+  const int64_t il = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (il > mo.n) return;
+  const double Ld = (double)g.L, coff = (double)g.c_off;
+  const double B = (double)((int64_t)1 << log_tile);
+  const double shift = (double)(g.w / 2 + 2);
+  int64_t t_min, t_max;
+  if (il == 0) {
+    t_min = 0;
+  } else {
+    const double lo = cell_pos(t, mo.start + il - 1, mo.T0, g.df, m, Ld, coff);
+    t_min = (int64_t)floor((lo + shift) / B) + 1;
   }
-  const int64_t idx = lo + lane;
-  const bool lt = (idx < hi) && (cell_pos(t, idx, T0, df, m, L, c_off) < target);
-  return lo + __popcll(__ballot(lt));
+  if (il == mo.n) {
+    t_max = tile_limit(t, mo, g, m, log_tile);
+  } else {
+    const double hi = cell_pos(t, mo.start + il, mo.T0, g.df, m, Ld, coff);
+    t_max = (int64_t)floor((hi + shift) / B);
+  }
+  if (t_min < 0) t_min = 0;
+  if (t_max > ntb - 1) t_max = ntb - 1;
+  int32_t* row = tb + ((int64_t)cw * (2 * g.H) + (m - 1)) * ntb;
+  for (int64_t q = t_min; q <= t_max; ++q) row[q] = (int32_t)il;
 }
 
 // Exponential-of-semicircle kernel exp(beta (sqrt(1 - z^2) - 1)) on |z| < 1.
@@ -196,7 +223,8 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ sigma,
                                                 const Moments* __restrict__ mom, Geom g,
-                                                int curve0, cplx<S>* __restrict__ grid) {
+                                                int curve0, const int32_t* __restrict__ tb,
+                                                int ntb, cplx<S>* __restrict__ grid) {
   constexpr bool EXACT = sizeof(S) == 8;
   constexpr int B = 1 << LOGB;
   constexpr int CPT = B / kNT;
@@ -205,7 +233,7 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
   __shared__ double s_fr[CH];
   __shared__ double s_re[CH];
   __shared__ double s_im[CH];
-  __shared__ int64_t s_rng[2];
+  __shared__ int s_first[kNT];
 
   const int tid = threadIdx.x;
   const int p = blockIdx.y;
@@ -221,7 +249,7 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
   const double beta = g.beta;
   const double Ld = (double)g.L;
   const double coff = (double)g.c_off;
-  const int64_t pa = mo.start, pb = mo.start + mo.n;
+  const int64_t pa = mo.start;
 
   double acc_re[CPT], acc_im[CPT];
 #pragma unroll
@@ -237,16 +265,10 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
     const bool both = (comp == 0) && (g.comp_m[p][1] == m);
     const int kind_a = g.comp_kind[p][comp];
     const int kind_b = both ? g.comp_kind[p][1] : -1;
-
-    const int wave = tid >> 6;
-    if (wave < 2) {
-      const double target = (wave == 0) ? (double)(a0 - hw - 2) : (double)(a0 + B + hw + 2);
-      const int64_t r = wave_lower_bound(t, pa, pb, target, mo.T0, g.df, m, Ld, coff);
-      if ((tid & 63) == 0) s_rng[wave] = r;
-    }
-    __syncthreads();
-    const int64_t i_lo = s_rng[0], i_hi = s_rng[1];
-    __syncthreads();
+    // No point of harmonic m reaches tiles past tile_limit - 2.
+    if ((int64_t)blockIdx.x + 2 > tile_limit(t, mo, g, m, LOGB)) continue;
+    const int32_t* row = tb + ((int64_t)cw * (2 * g.H) + (m - 1)) * ntb;
+    const int64_t i_lo = pa + row[blockIdx.x], i_hi = pa + row[blockIdx.x + 2];
 
     for (int64_t ch = i_lo; ch < i_hi; ch += CH) {
       const int cnt = (int)((i_hi - ch) < CH ? (i_hi - ch) : CH);
@@ -272,25 +294,33 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
         s_im[q] = sim;
       }
       __syncthreads();
-#pragma unroll
-      for (int u = 0; u < CPT; ++u) {
-        const int jl = tid + u * kNT;
-        // First point with j0 >= jl - hw - 1.
+      // First point with j0 >= c - hw - 1, found by binary search for every
+      // fourth cell (one search per thread); cells in between advance from it.
+      {
+        const int cs = tid * (B / kNT);
         int lo = 0, hi = cnt;
-        const int key = jl - hw - 1;
+        const int key = cs - hw - 1;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
           if (s_j0[mid] < key) lo = mid + 1;
           else hi = mid;
         }
+        s_first[tid] = lo;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int jl = tid + u * kNT;
+        int q = s_first[jl / (B / kNT)];
+        while (q < cnt && s_j0[q] < jl - hw - 1) ++q;
         double ar = acc_re[u], ai = acc_im[u];
-        for (int q = lo; q < cnt; ++q) {
-          const int j0 = s_j0[q];
+        for (int r = q; r < cnt; ++r) {
+          const int j0 = s_j0[r];
           if (j0 > jl + hw) break;
-          const double d = (double)(jl - j0) - s_fr[q];
+          const double d = (double)(jl - j0) - s_fr[r];
           const double phi = es_kernel<EXACT>(d * two_over_w, beta);
-          ar += phi * s_re[q];
-          ai += phi * s_im[q];
+          ar += phi * s_re[r];
+          ai += phi * s_im[r];
         }
         acc_re[u] = ar;
         acc_im[u] = ai;
@@ -337,27 +367,37 @@ hipError_t launch_moments(const double* t, const double* x, const double* sigma,
 
 hipError_t launch_spread(bool fp64, const double* t, const double* x, const double* sigma,
                          const Moments* mom, const Geom& g, int curve0, int n_curves,
-                         void* grid, int log_tile, hipStream_t st) {
+                         int64_t max_n, int32_t* tb, void* grid, int log_tile, hipStream_t st) {
   const int64_t tiles = g.L >> log_tile;
+  const int ntb = (int)tiles + 2;
+  dim3 gb((unsigned)((max_n + 1 + kNT - 1) / kNT), (unsigned)(2 * g.H), (unsigned)n_curves);
+  hipLaunchKernelGGL(k_tile_bounds, gb, dim3(kNT), 0, st, t, mom, g, curve0, log_tile, ntb, tb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   dim3 gr((unsigned)tiles, (unsigned)g.P, (unsigned)n_curves);
   if (log_tile == 10) {
     if (fp64)
       hipLaunchKernelGGL((k_spread<double, 10>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
-                         curve0, (cplx<double>*)grid);
+                         curve0, tb, ntb, (cplx<double>*)grid);
     else
       hipLaunchKernelGGL((k_spread<float, 10>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
-                         curve0, (cplx<float>*)grid);
+                         curve0, tb, ntb, (cplx<float>*)grid);
   } else if (log_tile == 11) {
     if (fp64)
       hipLaunchKernelGGL((k_spread<double, 11>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
-                         curve0, (cplx<double>*)grid);
+                         curve0, tb, ntb, (cplx<double>*)grid);
     else
       hipLaunchKernelGGL((k_spread<float, 11>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
-                         curve0, (cplx<float>*)grid);
+                         curve0, tb, ntb, (cplx<float>*)grid);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+size_t tile_bounds_bytes(const Geom& g, int log_tile, int n_curves) {
+  return sizeof(int32_t) * (size_t)n_curves * (size_t)(2 * g.H) *
+         (size_t)((g.L >> log_tile) + 2);
 }
 
 hipError_t launch_deconv_init(void* D, const Geom& g, const double* gl_x, const double* gl_w,
