@@ -156,14 +156,16 @@ __global__ __launch_bounds__(kNT) void k_adjoint(const cplx<R>* __restrict__ zc,
       double Lm[d][d];
       double inv[d];
       double z[d];
-#pragma unroll
-      for (int i = 0; i < d; ++i) {
-#pragma unroll
-        for (int j = 0; j <= i; ++j) {
+      static_for<0, d>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        static_for<0, i + 1>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
           double s = alpha_ij(i, j, Qr, Qi);
-#pragma unroll
-          for (int l = 0; l < j; ++l) s -= Lm[i][l] * Lm[j][l];
-          if (i == j) {
+          static_for<0, j>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            s -= Lm[i][l] * Lm[j][l];
+          });
+          if constexpr (i == j) {
             const double ajj = alpha_ij(i, i, Qr, Qi);
             if (s > eps * ajj && s > 0.0) {
               const double r = sqrt(s);
@@ -176,60 +178,58 @@ __global__ __launch_bounds__(kNT) void k_adjoint(const cplx<R>* __restrict__ zc,
           } else {
             Lm[i][j] = s * inv[j];
           }
-        }
+        });
         double s = beta_i(i, Pr, Pi);
-#pragma unroll
-        for (int l = 0; l < i; ++l) s -= Lm[i][l] * z[l];
+        static_for<0, i>([&](auto lc) {
+          constexpr int l = decltype(lc)::value;
+          s -= Lm[i][l] * z[l];
+        });
         z[i] = s * inv[i];
-      }
+      });
       // Accumulate dQ (index 0 = dW) and dP over H' = 1..H.
       double dQr[2 * H + 1], dQi[2 * H + 1], dPr[H + 1], dPi[H + 1];
-#pragma unroll
-      for (int m = 0; m <= 2 * H; ++m) {
+      static_for<0, 2 * H + 1>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
         dQr[m] = 0.0;
         dQi[m] = 0.0;
-      }
-#pragma unroll
-      for (int m = 0; m <= H; ++m) {
+      });
+      static_for<0, H + 1>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
         dPr[m] = 0.0;
         dPi[m] = 0.0;
-      }
+      });
       const O* gk = gin + (int64_t)c * H * nf + k;
-#pragma unroll
-      for (int hp = 1; hp <= H; ++hp) {
+      static_for<1, H + 1>([&](auto hc) {
+        constexpr int hp = decltype(hc)::value;
+        constexpr int dp = 2 * hp + 1;
         const double gv = (double)gk[(hp - 1) * nf];
-        const int dp = 2 * hp + 1;
-        double A[d];
-#pragma unroll
-        for (int ii = d - 1; ii >= 0; --ii) {
-          if (ii < dp) {
-            double s = z[ii];
-#pragma unroll
-            for (int l = ii + 1; l < d; ++l)
-              if (l < dp) s -= Lm[l][ii] * A[l];
-            A[ii] = s * inv[ii];
-          }
-        }
-#pragma unroll
-        for (int i = 1; i < d; ++i) {
-          if (i < dp) {
-            const double db = 2.0 * gv * A[i];
-            const int h = (i + 1) >> 1;
-            if (i & 1) dPi[h] += db;
-            else dPr[h] += db;
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < d; ++i) {
-#pragma unroll
-          for (int j = 0; j <= i; ++j) {
-            if (i < dp) {
-              const double v = -gv * A[i] * A[j] * (i == j ? 1.0 : 2.0);
-              alpha_adj(i, j, v, dQr, dQi);
-            }
-          }
-        }
-      }
+        // A' = L'^-T z' on the leading dp x dp block.
+        double A[dp];
+        static_for<0, dp>([&](auto rc) {
+          constexpr int ii = dp - 1 - decltype(rc)::value;
+          double s = z[ii];
+          static_for<ii + 1, dp>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            s -= Lm[l][ii] * A[l];
+          });
+          A[ii] = s * inv[ii];
+        });
+        static_for<1, dp>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          constexpr int h = (i + 1) >> 1;
+          const double db = 2.0 * gv * A[i];
+          if constexpr (i & 1) dPi[h] += db;
+          else dPr[h] += db;
+        });
+        static_for<0, dp>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          static_for<0, i + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const double v = -gv * A[i] * A[j] * (i == j ? 1.0 : 2.0);
+            alpha_adj(i, j, v, dQr, dQi);
+          });
+        });
+      });
       dW = dQr[0];
       // Transpose of D and of the unpacking; write the conjugated adjoint
       // spectrum at k and L - k of every packed grid.

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace fchi2 {
 
 constexpr int kHMax = 8;            // harmonics supported by the register solver
@@ -46,6 +48,16 @@ constexpr uint32_t kCurveFatal = CF_NONFINITE | CF_UNSORTED | CF_WRAP | CF_EMPTY
 
 // Bin flags.
 enum : uint8_t { BF_PIVOT = 1, BF_LOW_F = 2, BF_DC = 4 };
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B..E-1, so
+// every register-array index in the body is a constant (no scratch memory).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 template <typename R>
 struct cplx {

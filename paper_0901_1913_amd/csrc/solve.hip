@@ -142,14 +142,16 @@ __global__ __launch_bounds__(kNT) void k_solve(const cplx<R>* __restrict__ zc,
   double inv[d];
   double z[d];
   double acc = 0.0;
-#pragma unroll
-  for (int i = 0; i < d; ++i) {
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
+  static_for<0, d>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    static_for<0, i + 1>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
       double s = alpha_ij(i, j, Qr, Qi);
-#pragma unroll
-      for (int l = 0; l < j; ++l) s -= Lm[i][l] * Lm[j][l];
-      if (i == j) {
+      static_for<0, j>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        s -= Lm[i][l] * Lm[j][l];
+      });
+      if constexpr (i == j) {
         const double ajj = alpha_ij(i, i, Qr, Qi);
         if (s > eps * ajj && s > 0.0) {
           const double r = sqrt(s);
@@ -163,14 +165,16 @@ __global__ __launch_bounds__(kNT) void k_solve(const cplx<R>* __restrict__ zc,
       } else {
         Lm[i][j] = s * inv[j];
       }
-    }
+    });
     double s = beta_i(i, Pr, Pi);
-#pragma unroll
-    for (int l = 0; l < i; ++l) s -= Lm[i][l] * z[l];
+    static_for<0, i>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      s -= Lm[i][l] * z[l];
+    });
     z[i] = s * inv[i];
     acc += z[i] * z[i];
-    if (i >= 2 && (i & 1) == 0) o[(i / 2 - 1) * nf] = (O)acc;
-  }
+    if constexpr (i >= 2 && (i & 1) == 0) o[(i / 2 - 1) * nf] = (O)acc;
+  });
   if (flags) flags[(int64_t)c * nf + k] = fl;
 }
 
