@@ -185,6 +185,93 @@ def grad(t, x, sigma, terms):
     return gx, gs
 
 
+def log_chi2_sf_even(d, hp):
+    """ln of the upper tail of the chi2 law with 2 hp degrees of freedom at d.
+
+    Uses the Poisson identity: for even degrees of freedom the chi2 tail at d
+    equals P(N <= hp - 1) for N Poisson with mean d/2, so
+    ln Q = logsumexp_j (j ln u - u - ln j!), j < hp, u = d/2 (d < 0 -> 0).
+    Unlike a log of the tail itself, this stays finite for any d.
+    """
+    import scipy.special
+    d = np.maximum(np.asarray(d, dtype=np.float64), 0.0)
+    u = 0.5 * d
+    j = np.arange(hp, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        lu = np.log(u)
+    terms = j[:, None] * np.where(u > 0, lu, 0.0)[None, :] - u[None, :] \
+        - scipy.special.gammaln(j + 1.0)[:, None]
+    terms[1:, u == 0] = -np.inf                 # u^j = 0 for j >= 1 at u = 0
+    return scipy.special.logsumexp(terms, axis=0).reshape(np.shape(d))
+
+
+def log_significance(dchi2, k, H):
+    """ln p(f_k) = ln k + ln Q(Delta chi2 | 2H'), rows H' = 1..H (Section 3e).
+
+    p(f) is the chance probability of a reduction this large at a frequency
+    up to f: the bin index (trials so far) times the upper tail of the chi2
+    distribution with 2H' degrees of freedom (the model's extra parameters).
+    k = 0 gives ln p = -inf.
+    """
+    dchi2 = np.asarray(dchi2, dtype=np.float64)
+    k = np.asarray(k, dtype=np.float64)
+    out = np.empty_like(dchi2)
+    with np.errstate(divide="ignore"):
+        lk = np.log(k)
+    for hp in range(1, dchi2.shape[0] + 1):
+        out[hp - 1] = lk + log_chi2_sf_even(dchi2[hp - 1], hp)
+    return out
+
+
+def dchi2_adjusted(dchi2, chi2_0, n):
+    """Delta chi2_adj = Delta chi2 / (chi2_best / N_dof), rows H' = 1..H (Section 3e).
+
+    Reading of the printed denominator: chi2_best = chi2_0 - max_k Delta chi2
+    is the minimum chi2 of the best fit and N_dof = n - 2H' - 1 its degrees of
+    freedom, so the denominator is the best fit's reduced chi2 (the source
+    noise relative to the stated errors).  The maximum is over the bins given.
+    N_dof <= 0 gives NaN.
+    """
+    dchi2 = np.asarray(dchi2, dtype=np.float64)
+    out = np.empty_like(dchi2)
+    for hp in range(1, dchi2.shape[0] + 1):
+        best = chi2_0 - np.max(dchi2[hp - 1])
+        ndof = n - 2 * hp - 1
+        out[hp - 1] = dchi2[hp - 1] * ndof / best if ndof > 0 else np.nan
+    return out
+
+
+def top_candidates(dchi2_row, freqs, span, hp, K, k_lo=0):
+    """Best K candidate bins of one row (H' = hp) by ln p (Section 3e).
+
+    Candidates: bins k with k >= max(k_lo, 1), f_k >= 1/span, k <= N - 2 and
+    D[k] > D[k-1], D[k] >= D[k+1] (strict on the left: a plateau counts
+    once).  Ranked by ln p = ln k + ln Q(D[k] | 2hp) ascending, ties to the
+    lower k.  Also returns the largest D over the eligible bins (k up to
+    N - 1), from which chi2_best = chi2_0 - max follows.
+    Returns (idx [<=K], log_p [<=K], dmax or -inf).
+    """
+    d = np.asarray(dchi2_row, dtype=np.float64)
+    freqs = np.asarray(freqs, dtype=np.float64)
+    n = d.shape[0]
+    k = np.arange(n)
+    elig = (k >= max(int(k_lo), 1))
+    if span > 0:
+        elig &= freqs * span >= 1.0
+    dmax = float(np.max(d[elig])) if np.any(elig) else -np.inf
+    cand = []
+    for j in np.nonzero(elig)[0]:
+        if j > n - 2:
+            continue
+        if d[j] > d[j - 1] and d[j] >= d[j + 1]:
+            lp = np.log(j) + float(log_chi2_sf_even(np.array([d[j]]), hp)[0])
+            cand.append((lp, j))
+    cand.sort()
+    cand = cand[:K]
+    return (np.array([c[1] for c in cand], dtype=np.int64),
+            np.array([c[0] for c in cand], dtype=np.float64), dmax)
+
+
 def gate_mask(res, freqs, kappa_max):
     """Bins on which parity is judged: k >= 1, f >= 1/span, kappa <= kappa_max."""
     freqs = np.asarray(freqs, dtype=np.float64)

@@ -8,6 +8,7 @@ the null distribution of Delta chi2 (Section 2 and 3e: chi2 with 2H degrees of
 freedom), the printed H = 2 normal matrix of Section 3c, and finite
 differences for the closed-form gradient.
 """
+import math
 import os
 
 import numpy as np
@@ -248,3 +249,56 @@ def test_rel_err_floor():
     d_gpu = d_ora + 0.01
     e = ora.rel_err(d_gpu, d_ora)
     np.testing.assert_allclose(e, [[0.01 / 2, 0.01 / 10], [0.01 / 4, 0.01 / 20]])
+
+
+def test_log_significance_even_dof_closed_form():
+    """Upper chi2 tail with 2H dof: exp(-x/2) sum_{j<H} (x/2)^j / j!, and scipy's
+    chi2.logsf where that does not underflow."""
+    x = np.array([[0.0, 0.5, 3.0, 40.0, 700.0, 1400.0, 3e4, 2e6]] * 8)
+    k = np.array([1, 2, 10, 1000, 7, 3, 123456, 5])
+    got = ora.log_significance(x, k, 8)
+    for hp in range(1, 9):
+        for j in range(x.shape[1]):
+            xx = x[hp - 1, j]
+            s = sum((xx / 2) ** i / math.factorial(i) for i in range(hp))
+            ref = math.log(k[j]) - xx / 2 + math.log(s)
+            assert abs(got[hp - 1, j] - ref) <= 1e-12 * max(1.0, abs(ref)), (hp, xx)
+            if xx <= 1400.0:
+                sp = math.log(k[j]) + scipy.stats.chi2.logsf(xx, 2 * hp)
+                assert abs(got[hp - 1, j] - sp) <= 1e-10 * max(1.0, abs(sp)), (hp, xx)
+    assert np.isneginf(ora.log_significance(np.ones((1, 1)), np.array([0]), 1))[0, 0]
+
+
+def test_dchi2_adjusted_restores_chi2_for_underestimated_errors():
+    """Errors understated by 3x: the adjusted reduction is ~ Delta/9 (Section 3e)."""
+    rng = np.random.default_rng(81)
+    n, H = 400, 2
+    t = np.sort(rng.uniform(0, 100, n))
+    s = np.full(n, 0.1)
+    x = 3 * s * rng.standard_normal(n)              # true noise 3x the stated sigma
+    freqs = np.linspace(0.05, 3.0, 60)
+    res = ora.dchi2(t, x, s, freqs, H)
+    adj = ora.dchi2_adjusted(res["dchi2"], res["chi2_0"], n)
+    ratio = res["dchi2"] / adj                      # = chi2_best / N_dof per row
+    assert np.allclose(ratio, ratio[:, :1])
+    assert 6.0 < ratio[1, 0] < 12.0                 # ~ 9 = (3x)^2
+    best = np.argmax(res["dchi2"][1])
+    np.testing.assert_allclose(adj[1, best], res["dchi2"][1, best] * (n - 5)
+                               / (res["chi2_0"] - res["dchi2"][1, best]))
+
+
+def test_top_candidates_hand_row():
+    """Local maxima, plateau rule, eligibility and ln p ranking on a small row."""
+    import math
+    d = np.array([50.0, 1.0, 9.0, 2.0, 30.0, 30.0, 5.0, 7.0, 6.0, 40.0, 1.0, 3.0])
+    freqs = np.arange(d.size) * 0.1
+    idx, lp, dmax = ora.top_candidates(d, freqs, span=100.0, hp=1, K=10)
+    # maxima: 2 (9), 4 (30; plateau counted at its left end), 7 (7), 9 (40); 11 is the last bin
+    ref = sorted([(math.log(k) - d[k] / 2, k) for k in (2, 4, 7, 9)])
+    assert list(idx) == [k for _, k in ref]
+    np.testing.assert_allclose(lp, [v for v, _ in ref], rtol=1e-12)
+    assert dmax == 40.0                          # bin 0 (50) is not eligible
+    idx2, _, dmax2 = ora.top_candidates(d, freqs, span=100.0, hp=1, K=2, k_lo=5)
+    assert list(idx2) == [9, 7] and dmax2 == 40.0
+    idx3, _, _ = ora.top_candidates(d, freqs, span=3.0, hp=1, K=5)   # f >= 1/3 only
+    assert list(idx3) == [9, 4, 7]
