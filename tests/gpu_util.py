@@ -20,13 +20,18 @@ def to_dev(curves):
     return t, x, s
 
 
-def run_search(curves, precision=None, **plan_kw):
-    """Delta chi2 [n_curves, H, n_freq] (float64 numpy), chi2_0, flags, plan."""
+def run_search(curves, precision=None, tune=False, **plan_kw):
+    """Delta chi2 [n_curves, H, n_freq] (float64 numpy), chi2_0, flags, plan.
+
+    tune=True runs the autotuner first, as bench.py does before timing.
+    """
     import torch
     precision = precision or curves.precision
     plan = F.Plan(curves.offsets, curves.f_max, curves.H, curves.n_freq,
                   precision=precision, **plan_kw)
     t, x, s = to_dev(curves)
+    if tune:
+        print(f"[gpu] autotuned: {plan.autotune(t, x, s)}", flush=True)
     d, c0, fl = plan.search(t, x, s)
     torch.cuda.synchronize()
     return (d.double().cpu().numpy(), c0.cpu().numpy(), fl.cpu().numpy(), plan)

@@ -1,7 +1,7 @@
 """Parity at the full workload sizes, on bins the oracle evaluates one by one.
 
-Each test runs the search exactly as bench.py does (default plan for the
-workload) and compares seeded samples of bins, plus the neighbourhood of the
+Each test runs the search as bench.py does (default plan for the workload,
+autotuned before the search) and compares seeded samples of bins, plus the neighbourhood of the
 injected signal, with the FP64 oracle under the gate of the target
 (rel err <= 1e-5 on bins with k >= 1, f >= 1/span, kappa <= 1e2 mixed /
 1e6 FP64).
@@ -36,7 +36,7 @@ def _compare(cur, d, bins, precision, c=0, label="", r=None):
 def test_long_full_size():
     cur = synth.make("long")
     note("long full size (n=1e5, 2^22 bins, mixed)")
-    d, _, _, _ = run_search(cur)
+    d, _, _, _ = run_search(cur, tune=True)
     k0 = int(round(cur.n_freq / cur.f_max / 0.731))
     one = int(round(cur.n_freq / cur.f_max))  # 1 cycle/day alias region
     bins = np.unique(np.concatenate([sample_bins(cur.n_freq, 200, 2),
@@ -54,6 +54,7 @@ def test_diff_full_size_forward_and_gradient():
     plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed",
                   keep_for_backward=True)
     t, x, s = to_dev(cur)
+    plan.autotune(t, x, s)
     dd, _, _ = plan.search(t, x, s)
     span = cur.t[-1] - cur.t[0]
     df = cur.f_max / cur.n_freq
@@ -79,7 +80,7 @@ def test_stress_full_size_three_way():
     """Precision stress: mixed vs all-FP64 GPU vs the oracle."""
     cur = synth.make("stress")
     note("stress full size (n=1e6, 2^24 bins, H=8) mixed")
-    dm, _, flm, _ = run_search(cur, "mixed")
+    dm, _, flm, _ = run_search(cur, "mixed", tune=True)
     note("stress full size fp64")
     dd, _, _, _ = run_search(cur, "fp64")
     floor = (2.0 * np.arange(1, cur.H + 1))[:, None]
@@ -103,6 +104,7 @@ def test_batch_full_size_sampled_curves():
     note("batch full size (1e4 curves, 2^16 bins)")
     plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed", graph=True)
     t, x, s = to_dev(cur)
+    plan.autotune(t, x, s)
     st = torch.cuda.Stream()
     st.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(st):
