@@ -132,6 +132,8 @@ def batched_vs_plain(steps):
     plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision,
                   graph=True)
     ws = plan.workspace()
+    schedule = plan.autotune(t, x, s)
+    log(f"batch autotuned: {schedule}")
     dchi2 = torch.empty((cur.n_curves, cur.H, cur.n_freq), dtype=plan.out_dtype, device="cuda")
     chi2_0 = torch.empty(cur.n_curves, dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
@@ -158,6 +160,17 @@ def batched_vs_plain(steps):
         ms_p = e0.elapsed_time(e1)
         same = bool(torch.equal(ref, dchi2))
         log(f"plain loop: {ms_p:.3f} ms per pass (results identical: {same})")
+        del ref, dchi2
+        # Significance epilogue: K candidates per curve instead of the rows.
+        K = 16
+        plan.search_top(t, x, s, K=K, stream=stream)
+        e0.record(stream)
+        for _ in range(steps):
+            top = plan.search_top(t, x, s, K=K, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+        ms_top = e0.elapsed_time(e1) / steps
+        log(f"fused top-{K}: {ms_top:.3f} ms/step")
     plan.close()
     torch.cuda.synchronize()
     return {"workload": "batch", "n_curves": cur.n_curves, "n_total": int(cur.t.shape[0]),
@@ -165,7 +178,11 @@ def batched_vs_plain(steps):
             "batched_value": round(units / (ms_b * 1e-3), 1), "batched_ms_per_step": round(ms_b, 4),
             "plain_value": round(units / (ms_p * 1e-3), 1), "plain_ms_per_pass": round(ms_p, 3),
             "speedup": round(ms_p / ms_b, 3), "identical_outputs": same,
-            "unit": "freq*H/s"}
+            "schedule": schedule, "unit": "freq*H/s",
+            "fused_top16_value": round(units / (ms_top * 1e-3), 1),
+            "fused_top16_ms_per_step": round(ms_top, 4),
+            "rows_bytes": int(cur.n_curves * cur.H * cur.n_freq * 4),
+            "top16_bytes": int(sum(v.numel() * v.element_size() for v in top.values()))}
 
 
 def main(argv=None):
@@ -208,6 +225,10 @@ def main(argv=None):
     x = torch.from_numpy(cur.x).cuda()
     s = torch.from_numpy(cur.sigma).cuda()
     ws = plan.workspace()
+    t0 = time.perf_counter()
+    schedule = plan.autotune(t, x, s)
+    torch.cuda.synchronize()
+    log(f"autotuned in {time.perf_counter() - t0:.2f} s (not timed): {schedule}")
     dchi2 = torch.empty((1, cur.H, cur.n_freq), dtype=plan.out_dtype, device="cuda")
     chi2_0 = torch.empty(1, dtype=torch.float64, device="cuda")
     flags = torch.empty((1, cur.n_freq), dtype=torch.uint8, device="cuda")
@@ -264,6 +285,21 @@ def main(argv=None):
     stage_gbs = {k: round(nbytes[k] / (v[0] * 1e-3) / 1e9, 1) for k, v in st_avg.items()
                  if k in nbytes and v[0] > 0}
 
+    # Significance epilogue on the same plan: K candidates instead of the rows.
+    K = 16
+    top = plan.search_top(t, x, s, K=K)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(a.steps):
+        top = plan.search_top(t, x, s, K=K)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_top = ev0.elapsed_time(ev1) / a.steps
+    log(f"fused top-{K}: {ms_top:.4f} ms/step")
+    signif = {"K": K, "ms_per_step": round(ms_top, 5), "value": round(units / (ms_top * 1e-3), 1),
+              "best_bins": top["idx"][0, :4].tolist(),
+              "best_log_p": [round(v, 3) for v in top["log_p"][0, :4].tolist()]}
+
     d_gpu = dchi2.double().cpu().numpy()[0]
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "freq*H/s", "n_gpus": 1,
@@ -276,6 +312,7 @@ def main(argv=None):
         "roofline": roof,
         "stages_ms_per_step": per_step,
         "stages_gbs": stage_gbs,
+        "significance": signif,
     }
     if not a.no_cpu_baseline:
         from oracle import fchi2_oracle as ora

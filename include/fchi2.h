@@ -180,6 +180,97 @@ fchi2_status_t fchi2_top_peaks(fchi2_plan_t plan, const void* dchi2, int32_t hro
                                void* stream);
 
 /*
+ * Significance epilogue (Section 3e), fused with the per-bin solve: runs the
+ * whole search but, instead of writing the Delta chi2 rows, keeps per curve
+ * the K candidate bins with the smallest
+ *     ln p(f_k) = ln k + ln Q(Delta chi2(k, H') | 2H'),   H' = hrow + 1,
+ * Q being the upper tail of the chi2 distribution with 2H' degrees of freedom
+ * (the number of trials so far is taken proportional to f, hence to k).
+ * Candidates are the strict local maxima D[k] > D[k-1], D[k] >= D[k+1] of row
+ * hrow over the eligible bins: k >= max(k_lo, 1), f_k >= 1/span (no
+ * FCHI2_BIN_LOW_F flag) and k <= n_freq - 2; ties in ln p go to the lower k.
+ * The Delta chi2 values are exactly those fchi2_search writes (same rounding),
+ * so both select the same bins.  Also returns the adjusted reduction
+ *     Delta chi2_adj = Delta chi2 * N_dof / chi2_best,
+ * with chi2_best = chi2_0 - (largest Delta chi2 of row hrow over the eligible
+ * bins, k up to n_freq - 1) and N_dof = n - 2H' - 1 (NaN when N_dof <= 0).
+ *  out->idx        device int64 [n_curves][K]: bins, best first; -1 past the
+ *                  last candidate (required)
+ *  out->log_p      device FP64 [n_curves][K]: ln p; NaN past the last (required)
+ *  out->dchi2      device FP64 [n_curves][K][H]: Delta chi2 for H' = 1..H at
+ *                  the bin (may be NULL)
+ *  out->dchi2_adj  device FP64 [n_curves][K] (may be NULL)
+ *  out->flags      device u8 [n_curves][K]: FCHI2_BIN_* flags of the bin
+ *                  (may be NULL)
+ *  out->chi2_best  device FP64 [n_curves]; NaN if no bin is eligible (may be NULL)
+ *  out->curve_flags device u8 [n_curves]: the FCHI2_CURVE_* bits of each
+ *                  curve; a curve with a fatal bit has no candidates (may be NULL)
+ *  chi2_0          device FP64 [n_curves] or NULL, as for fchi2_search
+ *  workspace       >= fchi2_search_top_workspace_bytes(plan, K) bytes, 256-byte
+ *                  aligned (the plan's workspace plus the per-wave candidate lists)
+ * K is in 1..64.  Runs eagerly (no graph replay); with
+ * FCHI2_KEEP_FOR_BACKWARD it leaves the state fchi2_backward needs.
+ * Errors: FCHI2_ERR_ARG (NULL, K, hrow, k_lo < 0, workspace), FCHI2_ERR_HIP.
+ */
+typedef struct {
+  int64_t* idx;
+  double* log_p;
+  double* dchi2;
+  double* dchi2_adj;
+  uint8_t* flags;
+  double* chi2_best;
+  uint8_t* curve_flags;
+} fchi2_top_out_t;
+size_t fchi2_search_top_workspace_bytes(fchi2_plan_t plan, int32_t K);
+fchi2_status_t fchi2_search_top(fchi2_plan_t plan, const double* t, const double* x,
+                                const double* sigma, void* workspace, size_t workspace_bytes,
+                                int32_t hrow, int64_t k_lo, int32_t K, double* chi2_0,
+                                const fchi2_top_out_t* out, void* stream);
+
+/*
+ * Fine search on the ungridded data (Section 3e): around K centre frequencies
+ * per curve, Delta chi2 is computed directly from the points (FP64 sums of
+ * w e^{+i 2 pi m f tau}, m = 1..2H, and w y e^{+i 2 pi m f tau}, m = 1..H,
+ * tau = t - T0 with T0 the curve's first time) at the R trial frequencies
+ *     f_r = f_center + half_width * (2 r / (R - 1) - 1),  r = 0..R-1
+ * (f_center alone when R = 1), then solved as in fchi2_search (FP64, pivot
+ * threshold 1e-13), whatever the plan's precision.  The best trial of row
+ * hrow (largest Delta chi2, ties to the lower r) is returned with its
+ * coefficients A = alpha^-1 beta of the H-harmonic model (eq. eqcoeffs; basis
+ * 1, sin(2 pi h f tau), cos(2 pi h f tau), h = 1..H; xbar added back to A_0;
+ * a dropped pivot leaves its coefficient at 0).  A centre that is NaN or
+ * <= 0, a trial frequency <= 0 and a curve with a fatal data flag give NaN
+ * outputs.  The grid of the plan is not used: only its curves, H and offsets.
+ *  f_center       device FP64 [n_curves][K] (e.g. k * f_max / n_freq of the
+ *                 candidates of fchi2_search_top, NaN for a missing one)
+ *  out->rows      device FP64 [n_curves][K][R][H]: Delta chi2 at every trial
+ *                 (may be NULL)
+ *  out->f_best    device FP64 [n_curves][K] (required)
+ *  out->dchi2_best device FP64 [n_curves][K][H] (required)
+ *  out->coef      device FP64 [n_curves][K][2H+1] (may be NULL)
+ *  out->flags     device u8 [n_curves][K]: FCHI2_BIN_PIVOT / FCHI2_BIN_LOW_F of
+ *                 the best trial, or the curve's FCHI2_CURVE_* bits (may be NULL)
+ *  scratch        device, >= fchi2_fine_scratch_bytes(plan, K, R) bytes,
+ *                 256-byte aligned
+ * K is in 1..256, R in 1..4096.  Sums over a curve's points are taken in a
+ * fixed order (deterministic).
+ * Errors: FCHI2_ERR_ARG (NULL, K, R, half_width, hrow, scratch), FCHI2_ERR_HIP.
+ */
+typedef struct {
+  double* rows;
+  double* f_best;
+  double* dchi2_best;
+  double* coef;
+  uint8_t* flags;
+} fchi2_fine_out_t;
+size_t fchi2_fine_scratch_bytes(fchi2_plan_t plan, int32_t K, int32_t R);
+fchi2_status_t fchi2_fine_search(fchi2_plan_t plan, const double* t, const double* x,
+                                 const double* sigma, const double* f_center, int32_t K,
+                                 int32_t R, double half_width, int32_t hrow, void* scratch,
+                                 size_t scratch_bytes, const fchi2_fine_out_t* out,
+                                 void* stream);
+
+/*
  * Measurement support.  fchi2_profile(plan, 1) makes every later
  * fchi2_search / fchi2_backward on the plan record a HIP event pair around
  * each kernel launch, on the stream of that call (graph replay is bypassed
@@ -200,7 +291,9 @@ fchi2_status_t fchi2_top_peaks(fchi2_plan_t plan, const void* dchi2, int32_t hro
 #define FCHI2_PROF_BWD_FFT 7
 #define FCHI2_PROF_BWD_GATHER 8
 #define FCHI2_PROF_BWD_FINAL 9
-#define FCHI2_PROF_STAGES 10
+#define FCHI2_PROF_TOP_MERGE 10
+#define FCHI2_PROF_FINE 11
+#define FCHI2_PROF_STAGES 12
 fchi2_status_t fchi2_profile(fchi2_plan_t plan, int32_t enable);
 fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* launches);
 

@@ -333,6 +333,52 @@ fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double
   return FCHI2_OK;
 }
 
+size_t top_ws_offset(const fchi2_plan_s* pl) { return align256(pl->ws_bytes); }
+
+size_t top_ws_bytes(const fchi2_plan_s* pl, int K) {
+  return top_ws_offset(pl) + top_scratch_bytes(pl->g.n_freq, pl->g.H, pl->wave_max, K);
+}
+
+// The forward chain with the significance epilogue in place of the rows.
+fchi2_status_t enqueue_search_top(fchi2_plan_s* pl, const double* t, const double* x,
+                                  const double* sigma, char* ws, int hrow, int64_t k_lo, int K,
+                                  double* chi2_0, const TopOut& out, hipStream_t st) {
+  const int nc = pl->desc.n_curves;
+  Moments* mom = (Moments*)(ws + pl->off_mom);
+  PROF_BEGIN(FCHI2_PROF_MOMENTS);
+  hipError_t e = launch_moments(t, x, sigma, pl->d_off, nc, pl->mom_bpc, pl->g,
+                                (MomPart*)(ws + pl->off_part), mom, chi2_0, st);
+  if (e != hipSuccess) return hip_fail(e, "moments");
+  PROF_END();
+  const bool keep = pl->desc.flags & FCHI2_KEEP_FOR_BACKWARD;
+  const size_t zc_curve = (size_t)pl->g.P * 2 * pl->g.n_freq * pl->elem;
+  const TopScratch sc = top_scratch_carve(ws + top_ws_offset(pl), pl->g.n_freq, pl->g.H,
+                                          pl->wave_max, K);
+  for (int c0 = 0; c0 < nc; c0 += pl->wave) {
+    const int nw = (nc - c0) < pl->wave ? (nc - c0) : pl->wave;
+    void* gA = ws + pl->off_gA;
+    void* gB = ws + pl->off_gB;
+    void* zc = ws + pl->off_zc + (keep ? (size_t)c0 * zc_curve : 0);
+    PROF_BEGIN(FCHI2_PROF_SPREAD);
+    e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n,
+                      (int32_t*)(ws + pl->off_tb), gA, pl->log_tile, st);
+    if (e != hipSuccess) return hip_fail(e, "spread");
+    PROF_END();
+    fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st);
+    if (s != FCHI2_OK) return s;
+    PROF_BEGIN(FCHI2_PROF_SOLVE);
+    e = launch_solve_top(pl->fp64, zc, pl->d_D, mom, pl->g, c0, nw, pl->eps_piv, hrow, k_lo, K,
+                         sc, st);
+    if (e != hipSuccess) return hip_fail(e, "solve with candidate selection");
+    PROF_END();
+    PROF_BEGIN(FCHI2_PROF_TOP_MERGE);
+    e = launch_top_merge(mom, pl->g, c0, nw, hrow, K, sc, out, st);
+    if (e != hipSuccess) return hip_fail(e, "candidate merge");
+    PROF_END();
+  }
+  return FCHI2_OK;
+}
+
 fchi2_status_t check_ws(fchi2_plan_s* pl, void* ws, size_t bytes) {
   if (!ws) return fail(FCHI2_ERR_ARG, "workspace is NULL");
   if (((uintptr_t)ws & 255) != 0) return fail(FCHI2_ERR_ARG, "workspace must be 256-byte aligned");
@@ -680,6 +726,84 @@ fchi2_status_t fchi2_top_peaks(fchi2_plan_t plan, const void* dchi2, int32_t hro
                               plan->desc.n_curves, k_lo, K, scratch, out_idx,
                               (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "top peaks");
+  return FCHI2_OK;
+}
+
+size_t fchi2_search_top_workspace_bytes(fchi2_plan_t plan, int32_t K) {
+  if (!plan || K < 1 || K > 64) return 0;
+  return top_ws_bytes(plan, K);
+}
+
+fchi2_status_t fchi2_search_top(fchi2_plan_t plan, const double* t, const double* x,
+                                const double* sigma, void* workspace, size_t workspace_bytes,
+                                int32_t hrow, int64_t k_lo, int32_t K, double* chi2_0,
+                                const fchi2_top_out_t* out, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
+  if (!t || !x || !sigma || !out || !out->idx || !out->log_p)
+    return fail(FCHI2_ERR_ARG, "t, x, sigma, out, out->idx and out->log_p must not be NULL");
+  if (K < 1 || K > 64) return fail(FCHI2_ERR_ARG, "K must be in 1..64");
+  if (hrow < 0 || hrow >= plan->g.H) return fail(FCHI2_ERR_ARG, "hrow must be in 0..H-1");
+  if (k_lo < 0) return fail(FCHI2_ERR_ARG, "k_lo must be >= 0");
+  fchi2_status_t s = check_ws(plan, workspace, workspace_bytes);
+  if (s != FCHI2_OK) return s;
+  if (workspace_bytes < top_ws_bytes(plan, K))
+    return fail(FCHI2_ERR_ARG, "workspace too small for K = %d: %zu < %zu bytes", K,
+                workspace_bytes, top_ws_bytes(plan, K));
+  plan->last_ws = workspace;
+  TopOut o{out->idx, out->log_p, out->dchi2, out->dchi2_adj, out->flags, out->chi2_best,
+           out->curve_flags};
+  return enqueue_search_top(plan, t, x, sigma, (char*)workspace, hrow, k_lo, K, chi2_0, o,
+                            (hipStream_t)stream);
+}
+
+size_t fchi2_fine_scratch_bytes(fchi2_plan_t plan, int32_t K, int32_t R) {
+  if (!plan || K < 1 || K > 256 || R < 1 || R > 4096) return 0;
+  const int nc = plan->desc.n_curves;
+  return align256(sizeof(Moments) * (size_t)nc) +
+         align256(sizeof(MomPart) * (size_t)nc * plan->mom_bpc) +
+         align256(fine_part_bytes(plan->g.H, nc, plan->max_n, K, R));
+}
+
+fchi2_status_t fchi2_fine_search(fchi2_plan_t plan, const double* t, const double* x,
+                                 const double* sigma, const double* f_center, int32_t K,
+                                 int32_t R, double half_width, int32_t hrow, void* scratch,
+                                 size_t scratch_bytes, const fchi2_fine_out_t* out,
+                                 void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
+  if (!t || !x || !sigma || !f_center || !out || !out->f_best || !out->dchi2_best)
+    return fail(FCHI2_ERR_ARG,
+                "t, x, sigma, f_center, out, out->f_best and out->dchi2_best must not be NULL");
+  if (K < 1 || K > 256) return fail(FCHI2_ERR_ARG, "K must be in 1..256");
+  if (R < 1 || R > 4096) return fail(FCHI2_ERR_ARG, "R must be in 1..4096");
+  if (!(half_width >= 0.0) || !std::isfinite(half_width))
+    return fail(FCHI2_ERR_ARG, "half_width must be finite and >= 0");
+  if (hrow < 0 || hrow >= plan->g.H) return fail(FCHI2_ERR_ARG, "hrow must be in 0..H-1");
+  if (!scratch) return fail(FCHI2_ERR_ARG, "scratch is NULL");
+  if (((uintptr_t)scratch & 255) != 0) return fail(FCHI2_ERR_ARG, "scratch must be 256-byte aligned");
+  const size_t need = fchi2_fine_scratch_bytes(plan, K, R);
+  if (scratch_bytes < need)
+    return fail(FCHI2_ERR_ARG, "scratch too small: %zu < %zu bytes", scratch_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  fchi2_plan_s* pl = plan;
+  const int nc = plan->desc.n_curves;
+  char* sc = (char*)scratch;
+  Moments* mom = (Moments*)sc;
+  MomPart* part = (MomPart*)(sc + align256(sizeof(Moments) * (size_t)nc));
+  double* sums = (double*)(sc + align256(sizeof(Moments) * (size_t)nc) +
+                           align256(sizeof(MomPart) * (size_t)nc * plan->mom_bpc));
+  PROF_BEGIN(FCHI2_PROF_MOMENTS);
+  hipError_t e = launch_moments(t, x, sigma, plan->d_off, nc, plan->mom_bpc, plan->g, part, mom,
+                                nullptr, st);
+  if (e != hipSuccess) return hip_fail(e, "moments");
+  PROF_END();
+  FineOut o{out->rows, out->f_best, out->dchi2_best, out->coef, out->flags};
+  PROF_BEGIN(FCHI2_PROF_FINE);
+  e = launch_fine(t, x, sigma, mom, plan->g.H, nc, plan->max_n, f_center, K, R, half_width, sums,
+                  hrow, o, st);
+  if (e != hipSuccess) return hip_fail(e, "fine search");
+  PROF_END();
   return FCHI2_OK;
 }
 

@@ -70,4 +70,48 @@ hipError_t launch_peaks(bool fp64, const void* dchi2, int64_t n_freq, int H, int
                         hipStream_t st);
 size_t peaks_scratch_bytes(int64_t n_freq, int n_curves, int K);
 
+// Per-block candidate lists of the significance epilogue (one wave of curves).
+struct TopScratch {
+  double* score;   // [curve][block][K] ln p, ascending per block (+inf: empty)
+  int64_t* k;      // [curve][block][K] bin (-1: empty)
+  uint8_t* flag;   // [curve][block][K] bin flags
+  double* d;       // [curve][block][K][H] Delta chi2 rows at the bin
+  double* bmax;    // [curve][block] largest eligible Delta chi2 of the ranked row
+};
+// Per-curve results (absolute curve index); any pointer but idx and log_p may be null.
+struct TopOut {
+  int64_t* idx;
+  double* log_p;
+  double* dchi2;      // [curve][K][H]
+  double* dchi2_adj;  // [curve][K]
+  uint8_t* flags;     // [curve][K]
+  double* chi2_best;  // [curve]
+  uint8_t* curve_flags;  // [curve]
+};
+int top_blocks(int64_t n_freq);
+size_t top_scratch_bytes(int64_t n_freq, int H, int n_curves, int K);
+TopScratch top_scratch_carve(void* base, int64_t n_freq, int H, int n_curves, int K);
+// Fused per-bin solve and per-block candidate selection.
+hipError_t launch_solve_top(bool fp64, const void* zc, const void* D, const Moments* mom,
+                            const Geom& g, int curve0, int n_curves, double eps_piv, int hrow,
+                            int64_t k_lo, int K, const TopScratch& sc, hipStream_t st);
+// Per-curve merge of the block lists, significance and adjusted reduction.
+hipError_t launch_top_merge(const Moments* mom, const Geom& g, int curve0, int n_curves,
+                            int hrow, int K, const TopScratch& sc, const TopOut& out,
+                            hipStream_t st);
+
+// Fine search on the ungridded points around given centre frequencies.
+struct FineOut {
+  double* rows;        // [curve][K][R][H] or null
+  double* f_best;      // [curve][K]
+  double* dchi2_best;  // [curve][K][H]
+  double* coef;        // [curve][K][2H+1] or null
+  uint8_t* flags;      // [curve][K] or null
+};
+int fine_chunks(int64_t max_n);
+size_t fine_part_bytes(int H, int n_curves, int64_t max_n, int K, int R);
+hipError_t launch_fine(const double* t, const double* x, const double* sigma, const Moments* mom,
+                       int H, int n_curves, int64_t max_n, const double* fc, int K, int R,
+                       double hw, double* part, int hrow, const FineOut& out, hipStream_t st);
+
 }  // namespace fchi2

@@ -1,21 +1,10 @@
-// Per-frequency normal equations and Delta chi2 for every H' = 1..H.
-//
-// For bin k the packed spectra give Q_m = Q(m f_k) (m = 1..2H) and
-// P_m = P(m f_k) (m = 1..H).  The normal matrix alpha and right-hand side beta
-// follow from the product-to-sum identities of Section 2 (equations
-// eqalphafirst..eqalpha and the beta terms), with C'(g) = Re Q(g f),
-// S'(g) = Im Q(g f), C'(-g) = C'(g), S'(-g) = -S'(g), Q(0) = W (the exact FP64
-// sum of weights) and beta_0 = Re P(0) = 0 after centring (Section 3b).
-// The basis order [1, sin f, cos f, ..., sin Hf, cos Hf] makes the H' model a
-// prefix of the H model, so one Cholesky factor alpha = L L^T and
-// z = L^-1 beta give Delta chi2(H') = sum_{j <= 2H'} z_j^2 for all H' at once
-// (eq. eqchix with chi2_0 - chi2_min = beta^T alpha^-1 beta, Section 3d).
-// A pivot below eps * alpha_jj is dropped (its direction adds nothing), which
-// gives least-squares semantics for rank-deficient bins; the bin is flagged.
+// Per-frequency Delta chi2 for every H' = 1..H: one thread per bin runs the
+// shared per-bin solve and writes all H rows and the bin's flags.
 #include <cmath>
 
 #include "fchi2_internal.h"
 #include "launch.h"
+#include "solve_bin.h"
 
 namespace fchi2 {
 
@@ -23,86 +12,7 @@ namespace {
 
 constexpr int kNT = 256;
 
-// Pair layout: pair p < H packs the weight grids (q_{2p+1}, q_{2p+2}); pair
-// p >= H packs the weighted-data grids (p_{2j+1}, p_{2j+2}), j = p - H, the
-// second part empty past H.
-template <int H>
-struct Layout {
-  static constexpr int P = H + (H + 1) / 2;
-};
-
-// Unpack pair spectra at bin k into Qr/Qi (m = 0..2H) and Pr/Pi (m = 0..H),
-// already multiplied by the deconvolution / origin-shift factor D[k].
-template <int H, typename R>
-__device__ __forceinline__ void load_spectra(const cplx<R>* __restrict__ zc, int64_t nf,
-                                             int64_t base_pair, int64_t k, cplx<double> Dk_,
-                                             double W, double* Qr, double* Qi, double* Pr,
-                                             double* Pi) {
-  constexpr int P = Layout<H>::P;
-  const double Dr = (double)Dk_.x, Di = (double)Dk_.y;
-  Qr[0] = W;
-  Qi[0] = 0.0;
-  Pr[0] = 0.0;
-  Pi[0] = 0.0;
-#pragma unroll
-  for (int pp = 0; pp < P; ++pp) {
-    const cplx<R> z0 = zc[((base_pair + pp) * 2 + 0) * nf + k];
-    const cplx<R> z1 = zc[((base_pair + pp) * 2 + 1) * nf + k];
-    const double ax = 0.5 * ((double)z0.x + (double)z1.x);
-    const double ay = 0.5 * ((double)z0.y - (double)z1.y);
-    const double bx = 0.5 * ((double)z0.y + (double)z1.y);
-    const double by = -0.5 * ((double)z0.x - (double)z1.x);
-    const double Ar = ax * Dr - ay * Di, Ai = ax * Di + ay * Dr;
-    const double Br = bx * Dr - by * Di, Bi = bx * Di + by * Dr;
-    if (pp < H) {
-      Qr[2 * pp + 1] = Ar;
-      Qi[2 * pp + 1] = Ai;
-      Qr[2 * pp + 2] = Br;
-      Qi[2 * pp + 2] = Bi;
-    } else {
-      const int j = pp - H;
-      Pr[2 * j + 1] = Ar;
-      Pi[2 * j + 1] = Ai;
-      if (2 * j + 2 <= H) {
-        Pr[2 * j + 2] = Br;
-        Pi[2 * j + 2] = Bi;
-      }
-    }
-  }
-}
-
-__device__ __forceinline__ double Cp(const double* Qr, int gdiff) {
-  return Qr[gdiff < 0 ? -gdiff : gdiff];
-}
-__device__ __forceinline__ double Sp(const double* Qi, int gdiff) {
-  return gdiff < 0 ? -Qi[-gdiff] : Qi[gdiff];
-}
-
-// alpha_{ij} for basis indices i >= j (0 = constant, 2h-1 = sin h, 2h = cos h).
-__device__ __forceinline__ double alpha_ij(int i, int j, const double* Qr, const double* Qi) {
-  if (j == 0) {
-    if (i == 0) return Qr[0];
-    const int h = (i + 1) >> 1;
-    return (i & 1) ? Qi[h] : Qr[h];
-  }
-  const int h = (i + 1) >> 1, hp = (j + 1) >> 1;
-  const bool si = (i & 1), sj = (j & 1);
-  if (si && sj) return 0.5 * (Cp(Qr, h - hp) - Cp(Qr, h + hp));
-  if (si && !sj) return 0.5 * (Sp(Qi, h + hp) + Sp(Qi, h - hp));
-  if (!si && sj) return 0.5 * (Sp(Qi, h + hp) - Sp(Qi, h - hp));
-  return 0.5 * (Cp(Qr, h - hp) + Cp(Qr, h + hp));
-}
-
-__device__ __forceinline__ double beta_i(int i, const double* Pr, const double* Pi) {
-  if (i == 0) return 0.0;
-  const int h = (i + 1) >> 1;
-  return (i & 1) ? Pi[h] : Pr[h];
-}
-
-template <typename O>
-__device__ __forceinline__ O nan_of() {
-  return (O)NAN;
-}
+using namespace solve_detail;
 
 template <int H, typename R, typename O>
 __global__ __launch_bounds__(kNT) void k_solve(const cplx<R>* __restrict__ zc,
@@ -110,71 +20,17 @@ __global__ __launch_bounds__(kNT) void k_solve(const cplx<R>* __restrict__ zc,
                                                const Moments* __restrict__ mom, Geom g,
                                                int curve0, double eps, O* __restrict__ out,
                                                uint8_t* __restrict__ flags) {
-  constexpr int d = 2 * H + 1;
-  constexpr int P = Layout<H>::P;
   const int64_t nf = g.n_freq;
   const int64_t k = (int64_t)blockIdx.x * kNT + threadIdx.x;
   const int cw = blockIdx.y;
   const int c = curve0 + cw;
   if (k >= nf) return;
   const Moments mo = mom[c];
+  O d[H];
+  const uint8_t fl = solve_bin<H, R, O>(zc, D, mo, g, cw, k, eps, d);
   O* o = out + (int64_t)c * H * nf + k;
-  if (mo.flags & kCurveFatal) {
 #pragma unroll
-    for (int h = 0; h < H; ++h) o[h * nf] = nan_of<O>();
-    if (flags) flags[(int64_t)c * nf + k] = (uint8_t)(mo.flags & 0xF8u);
-    return;
-  }
-  uint8_t fl = 0;
-  const double f = (double)k * g.df;
-  if (mo.span > 0.0 && f * mo.span < 1.0) fl |= BF_LOW_F;
-  if (k == 0) {
-#pragma unroll
-    for (int h = 0; h < H; ++h) o[h * nf] = (O)0;
-    if (flags) flags[(int64_t)c * nf + k] = (uint8_t)(fl | BF_DC);
-    return;
-  }
-
-  double Qr[2 * H + 1], Qi[2 * H + 1], Pr[H + 1], Pi[H + 1];
-  load_spectra<H, R>(zc, nf, (int64_t)cw * P, k, D[k], mo.W, Qr, Qi, Pr, Pi);
-
-  double Lm[d][d];
-  double inv[d];
-  double z[d];
-  double acc = 0.0;
-  static_for<0, d>([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    static_for<0, i + 1>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      double s = alpha_ij(i, j, Qr, Qi);
-      static_for<0, j>([&](auto lc) {
-        constexpr int l = decltype(lc)::value;
-        s -= Lm[i][l] * Lm[j][l];
-      });
-      if constexpr (i == j) {
-        const double ajj = alpha_ij(i, i, Qr, Qi);
-        if (s > eps * ajj && s > 0.0) {
-          const double r = sqrt(s);
-          Lm[i][i] = r;
-          inv[i] = 1.0 / r;
-        } else {
-          Lm[i][i] = 0.0;
-          inv[i] = 0.0;
-          fl |= BF_PIVOT;
-        }
-      } else {
-        Lm[i][j] = s * inv[j];
-      }
-    });
-    double s = beta_i(i, Pr, Pi);
-    static_for<0, i>([&](auto lc) {
-      constexpr int l = decltype(lc)::value;
-      s -= Lm[i][l] * z[l];
-    });
-    z[i] = s * inv[i];
-    acc += z[i] * z[i];
-    if constexpr (i >= 2 && (i & 1) == 0) o[(i / 2 - 1) * nf] = (O)acc;
-  });
+  for (int h = 0; h < H; ++h) o[h * nf] = d[h];
   if (flags) flags[(int64_t)c * nf + k] = fl;
 }
 

@@ -30,9 +30,12 @@ EXPORTS = (
     "fchi2_backward", "fchi2_top_peaks_scratch_bytes", "fchi2_top_peaks",
     "fchi2_destroy", "fchi2_status_string", "fchi2_last_error", "fchi2_profile",
     "fchi2_profile_read", "fchi2_autotune", "fchi2_plan_info",
+    "fchi2_search_top_workspace_bytes", "fchi2_search_top",
+    "fchi2_fine_scratch_bytes", "fchi2_fine_search",
 )
 PROF_STAGES = ("moments", "spread", "fft_first", "fft_mid", "fft_last", "solve",
-               "bwd_solve", "bwd_fft", "bwd_gather", "bwd_final")
+               "bwd_solve", "bwd_fft", "bwd_gather", "bwd_final", "top_merge",
+               "fine")
 
 
 class PlanDesc(ctypes.Structure):
@@ -46,6 +49,28 @@ class PlanDesc(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("kernel_width", ctypes.c_int32),
         ("curves_per_wave", ctypes.c_int32),
+    ]
+
+
+class TopOut(ctypes.Structure):
+    _fields_ = [
+        ("idx", ctypes.c_void_p),
+        ("log_p", ctypes.c_void_p),
+        ("dchi2", ctypes.c_void_p),
+        ("dchi2_adj", ctypes.c_void_p),
+        ("flags", ctypes.c_void_p),
+        ("chi2_best", ctypes.c_void_p),
+        ("curve_flags", ctypes.c_void_p),
+    ]
+
+
+class FineOut(ctypes.Structure):
+    _fields_ = [
+        ("rows", ctypes.c_void_p),
+        ("f_best", ctypes.c_void_p),
+        ("dchi2_best", ctypes.c_void_p),
+        ("coef", ctypes.c_void_p),
+        ("flags", ctypes.c_void_p),
     ]
 
 
@@ -99,6 +124,16 @@ def lib() -> ctypes.CDLL:
     L.fchi2_autotune.restype = ctypes.c_int
     L.fchi2_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), i32]
     L.fchi2_plan_info.restype = ctypes.c_int
+    L.fchi2_search_top_workspace_bytes.argtypes = [vp, i32]
+    L.fchi2_search_top_workspace_bytes.restype = sz
+    L.fchi2_search_top.argtypes = [vp, vp, vp, vp, vp, sz, i32, i64, i32, vp,
+                                   ctypes.POINTER(TopOut), vp]
+    L.fchi2_search_top.restype = ctypes.c_int
+    L.fchi2_fine_scratch_bytes.argtypes = [vp, i32, i32]
+    L.fchi2_fine_scratch_bytes.restype = sz
+    L.fchi2_fine_search.argtypes = [vp, vp, vp, vp, vp, i32, i32, ctypes.c_double, i32, vp, sz,
+                                    ctypes.POINTER(FineOut), vp]
+    L.fchi2_fine_search.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -170,13 +205,15 @@ class Plan:
         self._ws = None
 
     # -- memory -----------------------------------------------------------
-    def workspace(self, device="cuda"):
-        """Allocate (once) and return the plan's workspace tensor."""
+    def workspace(self, device="cuda", nbytes: int = 0):
+        """Allocate and return the plan's workspace tensor (grown to nbytes if needed;
+        growing discards the state a later backward() needs)."""
         torch = _torch()
-        if self._ws is None:
+        need = max(self.workspace_bytes, int(nbytes), 256)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
             # torch allocations are 512-byte aligned on ROCm.
-            self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8,
-                                   device=device)
+            self._ws = torch.empty(need, dtype=torch.uint8, device=device)
         return self._ws
 
     @property
@@ -226,6 +263,104 @@ class Plan:
             if flags is not None else ctypes.c_void_p(0),
             ctypes.c_void_p(_stream_handle(stream))))
         return dchi2, chi2_0, flags
+
+    def search_top(self, t, x, sigma, K: int = 16, hrow: Optional[int] = None, k_lo: int = 0,
+                   workspace=None, stream=None):
+        """Search with the significance epilogue: per curve the K bins of smallest
+        ln p = ln k + ln Q(Delta chi2 | 2H') among the local maxima of row hrow.
+
+        Returns a dict of device tensors: idx [n_curves, K] int64 (-1 past the
+        last candidate), log_p [n_curves, K], dchi2 [n_curves, K, H],
+        dchi2_adj [n_curves, K], flags [n_curves, K] uint8, chi2_best and
+        chi2_0 [n_curves], curve_flags [n_curves] uint8.
+        """
+        torch = _torch()
+        f64 = torch.float64
+        hrow = self.H - 1 if hrow is None else int(hrow)
+        dev = t.device
+        nc = self.n_curves
+        res = {
+            "idx": torch.empty((nc, K), dtype=torch.int64, device=dev),
+            "log_p": torch.empty((nc, K), dtype=f64, device=dev),
+            "dchi2": torch.empty((nc, K, self.H), dtype=f64, device=dev),
+            "dchi2_adj": torch.empty((nc, K), dtype=f64, device=dev),
+            "flags": torch.empty((nc, K), dtype=torch.uint8, device=dev),
+            "chi2_best": torch.empty(nc, dtype=f64, device=dev),
+            "chi2_0": torch.empty(nc, dtype=f64, device=dev),
+            "curve_flags": torch.empty(nc, dtype=torch.uint8, device=dev),
+        }
+        need = int(lib().fchi2_search_top_workspace_bytes(self._h, int(K)))
+        if need == 0:
+            raise FChi2Error(ERR_ARG, "K must be in 1..64")
+        ws = self.workspace(dev, need) if workspace is None else workspace
+        out = TopOut(*(ctypes.c_void_p(res[k].data_ptr()) for k in
+                       ("idx", "log_p", "dchi2", "dchi2_adj", "flags", "chi2_best",
+                        "curve_flags")))
+        _check(lib().fchi2_search_top(
+            self._h, _dev_ptr(t, f64, self.n_total, "t"), _dev_ptr(x, f64, self.n_total, "x"),
+            _dev_ptr(sigma, f64, self.n_total, "sigma"), ctypes.c_void_p(ws.data_ptr()),
+            ctypes.c_size_t(ws.numel()), int(hrow), int(k_lo), int(K),
+            ctypes.c_void_p(res["chi2_0"].data_ptr()), ctypes.byref(out),
+            ctypes.c_void_p(_stream_handle(stream))))
+        return res
+
+    def fine_search(self, t, x, sigma, f_center, R: int = 64,
+                    half_width: Optional[float] = None, hrow: Optional[int] = None,
+                    want_rows: bool = False, stream=None):
+        """Direct (ungridded) Delta chi2 at R trial frequencies around each centre.
+
+        f_center: device FP64 [n_curves, K] (NaN for none).  half_width defaults
+        to one grid step f_max / n_freq.  Returns a dict of device tensors:
+        f_best [n_curves, K], dchi2_best [n_curves, K, H], coef
+        [n_curves, K, 2H+1] (xbar added to A_0; basis in t - first time),
+        flags [n_curves, K] uint8 and, with want_rows, rows [n_curves, K, R, H].
+        """
+        torch = _torch()
+        f64 = torch.float64
+        if f_center.dim() != 2 or f_center.shape[0] != self.n_curves:
+            raise ValueError("f_center must have shape [n_curves, K]")
+        K = int(f_center.shape[1])
+        hw = self.f_max / self.n_freq if half_width is None else float(half_width)
+        hrow = self.H - 1 if hrow is None else int(hrow)
+        dev = t.device
+        nc, H = self.n_curves, self.H
+        res = {
+            "f_best": torch.empty((nc, K), dtype=f64, device=dev),
+            "dchi2_best": torch.empty((nc, K, H), dtype=f64, device=dev),
+            "coef": torch.empty((nc, K, 2 * H + 1), dtype=f64, device=dev),
+            "flags": torch.empty((nc, K), dtype=torch.uint8, device=dev),
+        }
+        if want_rows:
+            res["rows"] = torch.empty((nc, K, R, H), dtype=f64, device=dev)
+        nbytes = int(lib().fchi2_fine_scratch_bytes(self._h, K, int(R)))
+        if nbytes == 0:
+            raise FChi2Error(ERR_ARG, "K must be in 1..256 and R in 1..4096")
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        out = FineOut(
+            ctypes.c_void_p(res["rows"].data_ptr()) if want_rows else ctypes.c_void_p(0),
+            ctypes.c_void_p(res["f_best"].data_ptr()),
+            ctypes.c_void_p(res["dchi2_best"].data_ptr()),
+            ctypes.c_void_p(res["coef"].data_ptr()), ctypes.c_void_p(res["flags"].data_ptr()))
+        _check(lib().fchi2_fine_search(
+            self._h, _dev_ptr(t, f64, self.n_total, "t"), _dev_ptr(x, f64, self.n_total, "x"),
+            _dev_ptr(sigma, f64, self.n_total, "sigma"),
+            _dev_ptr(f_center, f64, nc * K, "f_center"), K, int(R), hw, int(hrow),
+            ctypes.c_void_p(scratch.data_ptr()), ctypes.c_size_t(nbytes), ctypes.byref(out),
+            ctypes.c_void_p(_stream_handle(stream))))
+        return res
+
+    def refine(self, t, x, sigma, f_center, levels: int = 3, R: int = 64,
+               hrow: Optional[int] = None, stream=None):
+        """Zoom around each centre: level 1 spans +-1 grid step; each further
+        level spans +-2 trial steps of the previous one around its best."""
+        hw = self.f_max / self.n_freq
+        res = None
+        for _ in range(max(1, int(levels))):
+            res = self.fine_search(t, x, sigma, f_center, R=R, half_width=hw, hrow=hrow,
+                                   stream=stream)
+            f_center = res["f_best"]
+            hw = 2.0 * hw / max(R - 1, 1)
+        return res
 
     def backward(self, t, x, sigma, grad_dchi2, grad_x=None, grad_sigma=None,
                  workspace=None, stream=None):

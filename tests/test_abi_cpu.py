@@ -80,4 +80,10 @@ def test_null_arguments():
     assert L.fchi2_profile_read(None, None, None) == F.ERR_ARG
     assert L.fchi2_workspace_bytes(None) == 0
     assert L.fchi2_top_peaks_scratch_bytes(None, 4) == 0
+    assert L.fchi2_search_top(None, None, None, None, None, 0, 0, 1, 4, None, None,
+                              None) == F.ERR_ARG
+    assert L.fchi2_search_top_workspace_bytes(None, 4) == 0
+    assert L.fchi2_fine_search(None, None, None, None, None, 4, 8, 0.1, 0, None, 0, None,
+                               None) == F.ERR_ARG
+    assert L.fchi2_fine_scratch_bytes(None, 4, 8) == 0
     L.fchi2_destroy(None)
