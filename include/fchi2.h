@@ -271,6 +271,36 @@ fchi2_status_t fchi2_fine_search(fchi2_plan_t plan, const double* t, const doubl
                                  void* stream);
 
 /*
+ * Shared-alpha search for many sources observed at the same times with
+ * errors proportional to one sigma (Section 5: the inverse normal matrix of a
+ * frequency is the same for all of them).  Source s has data x[s][i] and
+ * errors scale[s] * sigma[i]; its Delta chi2 equals fchi2_search on
+ * (t, x[s], scale[s] * sigma).  Here the weight grids, their FFT and the
+ * Cholesky factor of alpha are computed once per frequency and only beta is
+ * formed per source; Delta chi2 of source s is the base-weight value divided
+ * by scale[s]^2.
+ *  plan      a plan of ONE curve (offsets {0, n}: the shared time base), H <= 5
+ *  t, sigma  device FP64 [n], t ascending
+ *  x         device FP64 [n_sources][n]
+ *  scale     device FP64 [n_sources], > 0 (a source with a bad scale or data
+ *            gets NaN rows and chi2_0)
+ *  dchi2     device [n_sources][H][n_freq], float (MIXED) or double (FP64)
+ *  chi2_0    device FP64 [n_sources] or NULL
+ *  flags     device u8 [n_freq] or NULL: bin flags, shared by all sources (or
+ *            the FCHI2_CURVE_* bits of the time base if it is rejected)
+ *  workspace >= fchi2_search_multi_workspace_bytes(plan, n_sources) bytes,
+ *            256-byte aligned (sources are processed in waves bounding the
+ *            grid memory to ~8 GiB)
+ * No backward.  The workspace query returns 0 for an unsupported plan.
+ * Errors: FCHI2_ERR_ARG, FCHI2_ERR_UNSUPPORTED (H > 5), FCHI2_ERR_HIP.
+ */
+size_t fchi2_search_multi_workspace_bytes(fchi2_plan_t plan, int32_t n_sources);
+fchi2_status_t fchi2_search_multi(fchi2_plan_t plan, const double* t, const double* sigma,
+                                  const double* x, const double* scale, int32_t n_sources,
+                                  void* workspace, size_t workspace_bytes, void* dchi2,
+                                  double* chi2_0, uint8_t* flags, void* stream);
+
+/*
  * Measurement support.  fchi2_profile(plan, 1) makes every later
  * fchi2_search / fchi2_backward on the plan record a HIP event pair around
  * each kernel launch, on the stream of that call (graph replay is bypassed
@@ -299,7 +329,8 @@ fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* 
 
 /*
  * Autotuner.  Times every candidate schedule of the plan on the caller's data
- * (the FFT digit splits with the fewest passes, spreading tiles of 1024 or
+ * (the FFT digit splits with the fewest passes and the most balanced splits
+ * with one pass more, spreading tiles of 1024 or
  * 2048 cells, and waves of wave_max, wave_max/2, wave_max/4 curves) with HIP
  * events on `stream`, keeps the fastest in the plan, and appends it to the
  * text file `cache_path` (may be NULL) keyed by the shape bucket (H, n_freq,

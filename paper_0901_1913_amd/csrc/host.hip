@@ -140,8 +140,12 @@ bool plan_fft(int logL, int LE, FftPlan& fp) {
   return false;
 }
 
-// Every valid digit split of L = 2^logL with the smallest pass count
-// (more passes only add HBM traffic).
+// Valid digit splits of L = 2^logL for the autotuner: every split with the
+// smallest pass count, plus the most balanced splits with one pass more.  The
+// extra pass costs a full read and write of the grids, but larger tiles in T
+// (columns per tile) give longer contiguous runs: at L = 2^18 the two-pass
+// split 2^9 x 2^9 moves runs of 8 elements (64 B), three passes of 2^6 move
+// runs of 64.
 std::vector<FftPlan> fft_splits(int logL, int LE) {
   std::vector<FftPlan> out;
   FftPlan best{};
@@ -150,30 +154,44 @@ std::vector<FftPlan> fft_splits(int logL, int LE) {
     out.push_back(best);
     return out;
   }
-  const int np = best.np, lo = 4, hi = 9;
-  int total = 1;
-  for (int q = 0; q < np; ++q) total *= (hi - lo + 1);
-  int ln[kMaxPasses + 1];
-  for (int code = 0; code < total; ++code) {
-    int c = code, sum = 0;
-    for (int q = 1; q <= np; ++q) {
-      ln[q] = lo + c % (hi - lo + 1);
-      c /= (hi - lo + 1);
-      sum += ln[q];
-    }
-    if (sum != logL) continue;
+  const int lo = 4, hi = 9;
+  auto valid = [&](const int* ln, int np) {
     bool ok = LE - ln[np] <= ln[1];
     for (int q = 2; q < np && ok; ++q) {
       int tail = 0;
       for (int d = q + 1; d <= np; ++d) tail += ln[d];
       if (LE - ln[q] > tail) ok = false;
     }
-    if (!ok) continue;
-    FftPlan f{};
-    f.np = np;
-    f.logL = logL;
-    for (int q = 1; q <= np; ++q) f.logn[q] = ln[q];
-    out.push_back(f);
+    return ok;
+  };
+  for (int np = best.np; np <= best.np + 1 && np <= kMaxPasses; ++np) {
+    std::vector<FftPlan> found;
+    int total = 1;
+    for (int q = 0; q < np; ++q) total *= (hi - lo + 1);
+    int ln[kMaxPasses + 1];
+    int best_min = 0;
+    for (int code = 0; code < total; ++code) {
+      int c = code, sum = 0, mn = 99;
+      for (int q = 1; q <= np; ++q) {
+        ln[q] = lo + c % (hi - lo + 1);
+        c /= (hi - lo + 1);
+        sum += ln[q];
+        mn = ln[q] < mn ? ln[q] : mn;
+      }
+      if (sum != logL || !valid(ln, np)) continue;
+      FftPlan f{};
+      f.np = np;
+      f.logL = logL;
+      for (int q = 1; q <= np; ++q) f.logn[q] = ln[q];
+      if (np == best.np) {
+        out.push_back(f);
+      } else if (mn >= best_min) {
+        if (mn > best_min) found.clear();
+        best_min = mn;
+        found.push_back(f);
+      }
+    }
+    out.insert(out.end(), found.begin(), found.end());
   }
   return out;
 }
@@ -258,7 +276,9 @@ hipError_t prof_mark(fchi2_plan_s* pl, int stage, hipStream_t st) {
   } while (0)
 
 fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void* zc,
-                           const Moments* mom, int curve0, int nw, hipStream_t st) {
+                           const Moments* mom, int curve0, int nw, hipStream_t st,
+                           const Geom* geom = nullptr) {
+  const Geom& g = geom ? *geom : pl->g;
   const FftPlan& fp = pl->fp;
   const int LE = fft_tile_log();
   FftPassArgs a{};
@@ -273,7 +293,7 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
     a.kind = PASS_SINGLE;
     a.q = 1;
     PROF_BEGIN(mode == MODE_FWD ? FCHI2_PROF_FFT_LAST : FCHI2_PROF_BWD_FFT);
-    hipError_t e = launch_fft_pass(pl->fp64, a, fp.logL, 0, gA, gA, mom, pl->g, pl->d_tw_stage,
+    hipError_t e = launch_fft_pass(pl->fp64, a, fp.logL, 0, gA, gA, mom, g, pl->d_tw_stage,
                                    pl->d_tw_small, nw, 1, st);
     if (e != hipSuccess) return hip_fail(e, "fft single pass");
     PROF_END();
@@ -284,7 +304,7 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
     a.kind = (q == fp.np) ? PASS_FIRST : (q == 1 ? PASS_LAST : PASS_MID);
     const int logn = fp.logn[q];
     const int logt = LE - logn;
-    const int64_t ncols = pl->g.L >> logn;
+    const int64_t ncols = g.L >> logn;
     const void* in = (q == fp.np) ? gA : gB;
     void* out = gB;
     const int stage = mode == MODE_BWD ? FCHI2_PROF_BWD_FFT
@@ -292,7 +312,7 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
                       : a.kind == PASS_MID   ? FCHI2_PROF_FFT_MID
                                              : FCHI2_PROF_FFT_LAST;
     PROF_BEGIN(stage);
-    hipError_t e = launch_fft_pass(pl->fp64, a, logn, logt, in, out, mom, pl->g, pl->d_tw_stage,
+    hipError_t e = launch_fft_pass(pl->fp64, a, logn, logt, in, out, mom, g, pl->d_tw_stage,
                                    pl->d_tw_small, nw, ncols, st);
     if (e != hipSuccess) return hip_fail(e, "fft pass");
     PROF_END();
@@ -374,6 +394,103 @@ fchi2_status_t enqueue_search_top(fchi2_plan_s* pl, const double* t, const doubl
     PROF_BEGIN(FCHI2_PROF_TOP_MERGE);
     e = launch_top_merge(mom, pl->g, c0, nw, hrow, K, sc, out, st);
     if (e != hipSuccess) return hip_fail(e, "candidate merge");
+    PROF_END();
+  }
+  return FCHI2_OK;
+}
+
+// Sources sharing one time base (shared-alpha search): geometry of the weight
+// grids (the first H pairs of the plan's layout) and of one source's data
+// grids (the remaining ceil(H/2) pairs), and the workspace layout.
+struct MultiLayout {
+  Geom gq, gp;
+  int wave = 1;
+  size_t off_mt = 0, off_pt = 0, off_ms = 0, off_ps = 0, off_tb = 0, off_gA = 0, off_gB = 0,
+         off_zq = 0, off_zp = 0, bytes = 0;
+};
+
+MultiLayout multi_layout(const fchi2_plan_s* pl, int S) {
+  MultiLayout m;
+  m.gq = pl->g;
+  m.gq.P = pl->g.H;
+  m.gp = pl->g;
+  const int pd = (pl->g.H + 1) / 2;
+  m.gp.P = pd;
+  for (int j = 0; j < pd; ++j)
+    for (int c = 0; c < 2; ++c) {
+      m.gp.comp_m[j][c] = pl->g.comp_m[pl->g.H + j][c];
+      m.gp.comp_kind[j][c] = pl->g.comp_kind[pl->g.H + j][c];
+    }
+  for (int j = pd; j < kMaxPairs; ++j)
+    for (int c = 0; c < 2; ++c) m.gp.comp_m[j][c] = 0;
+  const size_t grid_src = (size_t)pd * (size_t)pl->g.L * pl->elem;
+  size_t cap = ((size_t)8 << 30) / (2 * grid_src);
+  if (cap < 1) cap = 1;
+  m.wave = (int)(cap < (size_t)S ? cap : (size_t)S);
+  const size_t pairs = std::max<size_t>((size_t)pl->g.H, (size_t)m.wave * pd);
+  size_t off = 0;
+  m.off_mt = off;
+  off = align256(off + sizeof(Moments));
+  m.off_pt = off;
+  off = align256(off + sizeof(MomPart) * (size_t)pl->mom_bpc);
+  m.off_ms = off;
+  off = align256(off + sizeof(Moments) * (size_t)S);
+  m.off_ps = off;
+  off = align256(off + sizeof(MomPart) * (size_t)S * pl->mom_bpc);
+  m.off_tb = off;
+  off = align256(off + tile_bounds_bytes(pl->g, 10, 1));
+  m.off_gA = off;
+  off = align256(off + pairs * (size_t)pl->g.L * pl->elem);
+  m.off_gB = off;
+  off = align256(off + pairs * (size_t)pl->g.L * pl->elem);
+  m.off_zq = off;
+  off = align256(off + (size_t)pl->g.H * 2 * (size_t)pl->g.n_freq * pl->elem);
+  m.off_zp = off;
+  off = align256(off + (size_t)m.wave * pd * 2 * (size_t)pl->g.n_freq * pl->elem);
+  m.bytes = off;
+  return m;
+}
+
+fchi2_status_t enqueue_multi(fchi2_plan_s* pl, const MultiLayout& m, const double* t,
+                             const double* sigma, const double* x, const double* scale, int S,
+                             char* ws, void* dchi2, double* chi2_0, uint8_t* flags,
+                             hipStream_t st) {
+  Moments* mt = (Moments*)(ws + m.off_mt);
+  Moments* ms = (Moments*)(ws + m.off_ms);
+  int32_t* tb = (int32_t*)(ws + m.off_tb);
+  void* gA = ws + m.off_gA;
+  void* gB = ws + m.off_gB;
+  void* zq = ws + m.off_zq;
+  void* zp = ws + m.off_zp;
+  PROF_BEGIN(FCHI2_PROF_MOMENTS);
+  // The shared time base: sigma stands in for the data (only the weights,
+  // T0, span and the validity of t and sigma are used).
+  hipError_t e = launch_moments(t, sigma, sigma, pl->d_off, 1, pl->mom_bpc, pl->g,
+                                (MomPart*)(ws + m.off_pt), mt, nullptr, st);
+  if (e == hipSuccess)
+    e = launch_moments(t, x, sigma, pl->d_off, S, pl->mom_bpc, pl->g, (MomPart*)(ws + m.off_ps),
+                       ms, chi2_0, st, true, scale);
+  if (e != hipSuccess) return hip_fail(e, "moments");
+  PROF_END();
+  PROF_BEGIN(FCHI2_PROF_SPREAD);
+  e = launch_spread(pl->fp64, t, x, sigma, mt, m.gq, 0, 1, pl->max_n, tb, gA, pl->log_tile, st);
+  if (e != hipSuccess) return hip_fail(e, "spread (weights)");
+  PROF_END();
+  fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zq, mt, 0, 1, st, &m.gq);
+  if (s != FCHI2_OK) return s;
+  for (int s0 = 0; s0 < S; s0 += m.wave) {
+    const int nw = (S - s0) < m.wave ? (S - s0) : m.wave;
+    PROF_BEGIN(FCHI2_PROF_SPREAD);
+    e = launch_spread(pl->fp64, t, x, sigma, ms, m.gp, s0, nw, pl->max_n, tb, gA, pl->log_tile,
+                      st, true);
+    if (e != hipSuccess) return hip_fail(e, "spread (sources)");
+    PROF_END();
+    s = enqueue_fft(pl, MODE_FWD, gA, gB, zp, ms, s0, nw, st, &m.gp);
+    if (s != FCHI2_OK) return s;
+    PROF_BEGIN(FCHI2_PROF_SOLVE);
+    e = launch_solve_multi(pl->fp64, zq, zp, pl->d_D, mt, ms, scale, pl->g, s0, nw, pl->eps_piv,
+                           dchi2, flags, st);
+    if (e != hipSuccess) return hip_fail(e, "shared-alpha solve");
     PROF_END();
   }
   return FCHI2_OK;
@@ -805,6 +922,34 @@ fchi2_status_t fchi2_fine_search(fchi2_plan_t plan, const double* t, const doubl
   if (e != hipSuccess) return hip_fail(e, "fine search");
   PROF_END();
   return FCHI2_OK;
+}
+
+size_t fchi2_search_multi_workspace_bytes(fchi2_plan_t plan, int32_t n_sources) {
+  if (!plan || n_sources < 1 || plan->desc.n_curves != 1 || plan->g.H > 5) return 0;
+  return multi_layout(plan, n_sources).bytes;
+}
+
+fchi2_status_t fchi2_search_multi(fchi2_plan_t plan, const double* t, const double* sigma,
+                                  const double* x, const double* scale, int32_t n_sources,
+                                  void* workspace, size_t workspace_bytes, void* dchi2,
+                                  double* chi2_0, uint8_t* flags, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
+  if (!t || !sigma || !x || !scale || !dchi2)
+    return fail(FCHI2_ERR_ARG, "t, sigma, x, scale and dchi2 must not be NULL");
+  if (plan->desc.n_curves != 1)
+    return fail(FCHI2_ERR_ARG, "the shared time base needs a plan of one curve");
+  if (plan->g.H > 5) return fail(FCHI2_ERR_UNSUPPORTED, "shared-alpha search supports H <= 5");
+  if (n_sources < 1) return fail(FCHI2_ERR_ARG, "n_sources must be >= 1");
+  if (!workspace) return fail(FCHI2_ERR_ARG, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0)
+    return fail(FCHI2_ERR_ARG, "workspace must be 256-byte aligned");
+  const MultiLayout m = multi_layout(plan, n_sources);
+  if (workspace_bytes < m.bytes)
+    return fail(FCHI2_ERR_ARG, "workspace too small: %zu < %zu bytes", workspace_bytes, m.bytes);
+  plan->last_ws = nullptr;  // no backward for this form
+  return enqueue_multi(plan, m, t, sigma, x, scale, n_sources, (char*)workspace, dchi2, chi2_0,
+                       flags, (hipStream_t)stream);
 }
 
 fchi2_status_t fchi2_profile(fchi2_plan_t plan, int32_t enable) {

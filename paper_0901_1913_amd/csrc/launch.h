@@ -19,15 +19,20 @@ struct FftPassArgs {
 
 // Moments, validity flags and chi2_0 of every curve: bpc workgroups per
 // curve reduce chunks into part[n_curves][bpc], then one pass combines them.
+// shared_t: every curve c uses the points [offsets[0], offsets[1]) of t and
+// sigma with data x[c * n + i]; scale (nullable): per-curve error scale, the
+// reported chi2_0 is divided by its square.
 hipError_t launch_moments(const double* t, const double* x, const double* sigma,
                           const int64_t* offsets, int n_curves, int bpc, const Geom& g,
-                          MomPart* part, Moments* mom, double* chi2_0, hipStream_t st);
+                          MomPart* part, Moments* mom, double* chi2_0, hipStream_t st,
+                          bool shared_t = false, const double* scale = nullptr);
 
 // Spread w and w*(x - xbar) of each curve of the wave onto its P packed grids.
 // tb: tile -> point-range table, tile_bounds_bytes(g, log_tile, n_curves).
 hipError_t launch_spread(bool fp64, const double* t, const double* x, const double* sigma,
                          const Moments* mom, const Geom& g, int curve0, int n_curves,
-                         int64_t max_n, int32_t* tb, void* grid, int log_tile, hipStream_t st);
+                         int64_t max_n, int32_t* tb, void* grid, int log_tile, hipStream_t st,
+                         bool share_tb = false);
 size_t tile_bounds_bytes(const Geom& g, int log_tile, int n_curves);
 
 // log2 of the elements of one FFT tile (rows x columns held in LDS).
@@ -46,6 +51,14 @@ hipError_t launch_deconv_init(void* D, const Geom& g, const double* gl_x, const 
 hipError_t launch_solve(bool fp64, const void* zc, const void* D, const Moments* mom,
                         const Geom& g, int curve0, int n_curves, double eps_piv, void* dchi2,
                         uint8_t* flags, hipStream_t st);
+
+// Shared-alpha solve for sources at the same times (H <= 5): alpha from the
+// weight spectra zq (slot 0, H pairs), beta per source from zp (ceil(H/2)
+// pairs per wave slot); rows of source s scaled by 1/scale[s]^2.
+hipError_t launch_solve_multi(bool fp64, const void* zq, const void* zp, const void* D,
+                              const Moments* mom_t, const Moments* mom_s, const double* scale,
+                              const Geom& g, int src0, int n_src, double eps_piv, void* dchi2,
+                              uint8_t* flags, hipStream_t st);
 
 // Adjoint of the solve: per-bin gradients into the packed adjoint spectra.
 hipError_t launch_adjoint_solve(bool fp64, const void* zc, const void* D, const Moments* mom,
@@ -77,6 +90,11 @@ struct TopScratch {
   uint8_t* flag;   // [curve][block][K] bin flags
   double* d;       // [curve][block][K][H] Delta chi2 rows at the bin
   double* bmax;    // [curve][block] largest eligible Delta chi2 of the ranked row
+  // merged lists of groups of up to 256 blocks
+  double* g_score;  // [curve][group][K]
+  int64_t* g_k;     // [curve][group][K]
+  int64_t* g_q;     // [curve][group][K] index of the record in the arrays above
+  double* g_max;    // [curve][group]
 };
 // Per-curve results (absolute curve index); any pointer but idx and log_p may be null.
 struct TopOut {

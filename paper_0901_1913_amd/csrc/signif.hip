@@ -23,9 +23,13 @@
 //
 // Phase 1 (fused with the per-bin solve): one block of 256 threads solves
 // 1024 consecutive bins, the first and last being halo bins whose values only
-// serve the neighbour test, keeps all H rows in LDS, sorts its 1022 owned
-// bins' keys (ln p, k) with a bitonic network and writes its K best in order.
-// Phase 2: one block per curve merges the sorted per-block lists.
+// serve the neighbour test, keeps all H rows in LDS and selects the K best of
+// its 1022 owned bins by a tournament: each thread keeps its four keys
+// (ln p, k) sorted, and each round takes the block minimum of the threads'
+// heads (wave shuffles, one barrier); the owner of the winner advances.  The
+// K winners are written in order.  Phase 2: the sorted per-block lists are
+// merged in groups of up to 256 (one list per thread, the same tournament),
+// and the group lists once more per curve, which gives the final K.
 #include <cmath>
 #include <cstdint>
 
@@ -70,9 +74,10 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
     uint8_t* __restrict__ rf, double* __restrict__ rd, double* __restrict__ bmax) {
   __shared__ O s_d[H][kSpan];
   __shared__ uint8_t s_fl[kSpan];
-  __shared__ double s_ks[kSpan];
-  __shared__ int s_ki[kSpan];
   __shared__ double s_red[kNT / 64];
+  __shared__ double t_s[2][kNT / 64];
+  __shared__ int t_i[2][kNT / 64];
+  __shared__ int s_win[64];
 
   const int tid = threadIdx.x;
   const int cw = blockIdx.y;
@@ -99,6 +104,8 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
   const int hp = hrow + 1;
   const int64_t k_first = k_lo > 1 ? k_lo : 1;
   double vmax = -INFINITY;
+  double ks[kBPT];
+  int ki[kBPT];
 #pragma unroll
   for (int r = 0; r < kBPT; ++r) {
     const int i = r * kNT + tid;
@@ -115,8 +122,8 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
           score = log((double)k) + log_q_even(v, hp);
       }
     }
-    s_ks[i] = score;
-    s_ki[i] = i;
+    ks[r] = score;
+    ki[r] = i;
   }
   // Block maximum of the eligible Delta chi2 (for chi2_best).
   for (int o = 32; o > 0; o >>= 1) {
@@ -124,34 +131,72 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
     vmax = other > vmax ? other : vmax;
   }
   if ((tid & 63) == 0) s_red[tid >> 6] = vmax;
-  __syncthreads();
 
-  // Bitonic sort of the kSpan keys, ascending.
-  for (int size = 2; size <= kSpan; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int p = tid; p < kSpan / 2; p += kNT) {  // pair index
-        const int a = ((p & ~(stride - 1)) << 1) | (p & (stride - 1));
-        const int b = a + stride;
-        const bool up = (a & size) == 0;
-        const double sa = s_ks[a], sb = s_ks[b];
-        const int ia = s_ki[a], ib = s_ki[b];
-        if (key_less(sb, ib, sa, ia) == up) {
-          s_ks[a] = sb;
-          s_ki[a] = ib;
-          s_ks[b] = sa;
-          s_ki[b] = ia;
-        }
+  // Sort the thread's own keys (compile-time network).
+#pragma unroll
+  for (int a = 0; a < kBPT; ++a) {
+#pragma unroll
+    for (int b = kBPT - 1; b > a; --b) {
+      if (key_less(ks[b], ki[b], ks[b - 1], ki[b - 1])) {
+        const double ts = ks[b];
+        const int ti = ki[b];
+        ks[b] = ks[b - 1];
+        ki[b] = ki[b - 1];
+        ks[b - 1] = ts;
+        ki[b - 1] = ti;
       }
-      __syncthreads();
     }
   }
+  // Tournament: K rounds of block arg-min over the threads' heads.  The two
+  // LDS buffers alternate, so one barrier per round suffices.
+  int head = 0;
+  int rounds = 0;
+  for (int r = 0; r < K; ++r) {
+    double sv = INFINITY;
+    int si = 0x7fffffff;
+#pragma unroll
+    for (int q = 0; q < kBPT; ++q) {
+      if (q == head) {
+        sv = ks[q];
+        si = ki[q];
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double os = __shfl_xor(sv, o);
+      const int oi = __shfl_xor(si, o);
+      if (key_less(os, oi, sv, si)) {
+        sv = os;
+        si = oi;
+      }
+    }
+    const int buf = r & 1;
+    if ((tid & 63) == 0) {
+      t_s[buf][tid >> 6] = sv;
+      t_i[buf][tid >> 6] = si;
+    }
+    __syncthreads();
+    double bs = t_s[buf][0];
+    int bi = t_i[buf][0];
+#pragma unroll
+    for (int w = 1; w < kNT / 64; ++w) {
+      if (key_less(t_s[buf][w], t_i[buf][w], bs, bi)) {
+        bs = t_s[buf][w];
+        bi = t_i[buf][w];
+      }
+    }
+    if (!(bs < INFINITY)) break;  // the same decision in every thread
+    if (tid == 0) s_win[r] = bi;
+    if ((bi & (kNT - 1)) == tid) ++head;
+    rounds = r + 1;
+  }
+  __syncthreads();
 
   const int64_t base = ((int64_t)cw * nblk + blockIdx.x) * K;
   if (tid < K) {
-    const double sc = s_ks[tid];
-    const int i = s_ki[tid];
-    const bool ok = sc < INFINITY;
-    rs[base + tid] = ok ? sc : INFINITY;
+    const bool ok = tid < rounds;
+    const int i = ok ? s_win[tid] : 0;
+    rs[base + tid] = ok ? log((double)(B0 - 1 + i)) + log_q_even((double)s_d[hrow][i], hp)
+                        : INFINITY;
     rk[base + tid] = ok ? B0 - 1 + i : -1;
     rf[base + tid] = ok ? s_fl[i] : 0;
 #pragma unroll
@@ -164,111 +209,138 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
   }
 }
 
-// Merge of the per-block sorted lists of one curve: K rounds, each taking the
-// smallest head key; the owner of the winning list advances its head.
+// One merge step: group g of curve slot cw takes up to 256 sorted lists (one
+// per thread; list l = g * 256 + tid of the nl lists of the curve) and keeps
+// their K smallest keys (ln p, k), in order, by the tournament of the solve
+// kernel.  Records are referred to by their index q in the phase-1 arrays
+// (in_q null: the input is phase 1 itself).  With `fin` set (one group per
+// curve) it writes the user outputs instead of a list.
 __global__ __launch_bounds__(kNT) void k_top_merge(
-    const double* __restrict__ rs, const int64_t* __restrict__ rk,
-    const uint8_t* __restrict__ rf, const double* __restrict__ rd,
-    const double* __restrict__ bmax, const Moments* __restrict__ mom, int curve0, int nblk,
-    int K, int H, int hrow, int64_t* __restrict__ out_idx, double* __restrict__ out_logp,
-    double* __restrict__ out_dchi2, double* __restrict__ out_adj,
-    uint8_t* __restrict__ out_flags, double* __restrict__ out_best,
-    uint8_t* __restrict__ out_cflags) {
-  extern __shared__ uint8_t s_head[];  // [nblk] current head of each list
-  __shared__ double r_s[kNT];
-  __shared__ int64_t r_k[kNT];
-  __shared__ int r_l[kNT];
-  __shared__ int64_t s_win[64];  // winning record index per round (-1: none)
-  __shared__ double s_mx[kNT];
+    const double* __restrict__ in_s, const int64_t* __restrict__ in_k,
+    const int64_t* __restrict__ in_q, const double* __restrict__ in_max, int nl, int K,
+    double* __restrict__ o_s, int64_t* __restrict__ o_k, int64_t* __restrict__ o_q,
+    double* __restrict__ o_max, int fin, const Moments* __restrict__ mom, int curve0, int H,
+    int hrow, const uint8_t* __restrict__ rf, const double* __restrict__ rd, TopOut out) {
+  __shared__ double t_s[2][kNT / 64];
+  __shared__ int64_t t_k[2][kNT / 64];
+  __shared__ int t_l[2][kNT / 64];
+  __shared__ double s_ws[64];   // winning score per round
+  __shared__ int64_t s_wk[64];  // winning bin per round
+  __shared__ int64_t s_wq[64];  // winning phase-1 record per round
+  __shared__ double s_mx[kNT / 64];
 
   const int tid = threadIdx.x;
-  const int cw = blockIdx.x;
-  const int c = curve0 + cw;
-  const Moments mo = mom[c];
-  const int64_t lbase = (int64_t)cw * nblk;
+  const int g = blockIdx.x;
+  const int cw = blockIdx.y;
+  const int ng = gridDim.x;
+  const int l = g * kNT + tid;
+  const int64_t lbase = ((int64_t)cw * nl + l) * K;  // this thread's list
 
   double mx = -INFINITY;
-  for (int l = tid; l < nblk; l += kNT) {
-    s_head[l] = 0;
-    const double v = bmax[lbase + l];
-    mx = v > mx ? v : mx;
+  if (l < nl) mx = in_max[(int64_t)cw * nl + l];
+  for (int o = 32; o > 0; o >>= 1) {
+    const double other = __shfl_xor(mx, o);
+    mx = other > mx ? other : mx;
   }
-  s_mx[tid] = mx;
-  __syncthreads();
-  for (int s = kNT / 2; s > 0; s >>= 1) {
-    if (tid < s && s_mx[tid + s] > s_mx[tid]) s_mx[tid] = s_mx[tid + s];
-    __syncthreads();
-  }
-  const double vmax = s_mx[0];
+  if ((tid & 63) == 0) s_mx[tid >> 6] = mx;
 
+  int head = 0;
+  int rounds = 0;
   for (int r = 0; r < K; ++r) {
-    double bs = INFINITY;
-    int64_t bk = INT64_MAX;
-    int bl = -1;
-    for (int l = tid; l < nblk; l += kNT) {
-      const int h = s_head[l];
-      if (h >= K) continue;
-      const int64_t q = (lbase + l) * K + h;
-      const int64_t k = rk[q];
-      if (k < 0) continue;
-      const double s = rs[q];
-      if (s < bs || (s == bs && k < bk)) {
-        bs = s;
-        bk = k;
-        bl = l;
+    double sv = INFINITY;
+    int64_t sk = INT64_MAX;
+    int sl = -1;
+    if (l < nl && head < K) {
+      const int64_t k = in_k[lbase + head];
+      if (k >= 0) {
+        sv = in_s[lbase + head];
+        sk = k;
+        sl = tid;
       }
     }
-    r_s[tid] = bs;
-    r_k[tid] = bk;
-    r_l[tid] = bl;
-    __syncthreads();
-    for (int s = kNT / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double os = r_s[tid + s];
-        const int64_t ok = r_k[tid + s];
-        if (r_l[tid + s] >= 0 && (r_l[tid] < 0 || os < r_s[tid] || (os == r_s[tid] && ok < r_k[tid]))) {
-          r_s[tid] = os;
-          r_k[tid] = ok;
-          r_l[tid] = r_l[tid + s];
-        }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double os = __shfl_xor(sv, o);
+      const int64_t ok = __shfl_xor(sk, o);
+      const int ol = __shfl_xor(sl, o);
+      if (ol >= 0 && (sl < 0 || os < sv || (os == sv && ok < sk))) {
+        sv = os;
+        sk = ok;
+        sl = ol;
       }
-      __syncthreads();
     }
-    if (tid == 0) {
-      const int wl = r_l[0];
-      if (wl >= 0) {
-        s_win[r] = (lbase + wl) * K + s_head[wl];
-        s_head[wl] = (uint8_t)(s_head[wl] + 1);
-      } else {
-        s_win[r] = -1;
-      }
+    const int buf = r & 1;
+    if ((tid & 63) == 0) {
+      t_s[buf][tid >> 6] = sv;
+      t_k[buf][tid >> 6] = sk;
+      t_l[buf][tid >> 6] = sl;
     }
     __syncthreads();
+    double bs = t_s[buf][0];
+    int64_t bk = t_k[buf][0];
+    int bl = t_l[buf][0];
+#pragma unroll
+    for (int w = 1; w < kNT / 64; ++w) {
+      const int ol = t_l[buf][w];
+      if (ol >= 0 && (bl < 0 || t_s[buf][w] < bs || (t_s[buf][w] == bs && t_k[buf][w] < bk))) {
+        bs = t_s[buf][w];
+        bk = t_k[buf][w];
+        bl = ol;
+      }
+    }
+    if (bl < 0) break;  // the same decision in every thread
+    if (bl == tid) {
+      const int64_t pos = lbase + head;
+      s_ws[r] = bs;
+      s_wk[r] = bk;
+      s_wq[r] = in_q ? in_q[pos] : pos;
+      ++head;
+    }
+    rounds = r + 1;
+  }
+  __syncthreads();
+  double gmax = s_mx[0];
+#pragma unroll
+  for (int w = 1; w < kNT / 64; ++w) gmax = s_mx[w] > gmax ? s_mx[w] : gmax;
+
+  if (!fin) {
+    const int64_t ob = ((int64_t)cw * ng + g) * K;
+    if (tid < K) {
+      const bool ok = tid < rounds;
+      o_s[ob + tid] = ok ? s_ws[tid] : INFINITY;
+      o_k[ob + tid] = ok ? s_wk[tid] : -1;
+      o_q[ob + tid] = ok ? s_wq[tid] : -1;
+    }
+    if (tid == 0) o_max[(int64_t)cw * ng + g] = gmax;
+    return;
   }
 
+  const int c = curve0 + cw;
+  const Moments mo = mom[c];
   const bool fatal = (mo.flags & kCurveFatal) != 0;
-  const double best = (fatal || !(vmax > -INFINITY)) ? (double)NAN : mo.chi2_0 - vmax;
+  const double best = (fatal || !(gmax > -INFINITY)) ? (double)NAN : mo.chi2_0 - gmax;
   const double ndof = (double)(mo.n - 2 * (hrow + 1) - 1);
-  if (tid == 0 && out_best) out_best[c] = best;
-  if (tid == 0 && out_cflags) out_cflags[c] = (uint8_t)(mo.flags & 0xF8u);
+  if (tid == 0) {
+    if (out.chi2_best) out.chi2_best[c] = best;
+    if (out.curve_flags) out.curve_flags[c] = (uint8_t)(mo.flags & 0xF8u);
+  }
   if (tid < K) {
-    const int64_t q = s_win[tid];
     const int64_t o = (int64_t)c * K + tid;
-    if (q >= 0) {
-      out_idx[o] = rk[q];
-      out_logp[o] = rs[q];
+    if (tid < rounds) {
+      const int64_t q = s_wq[tid];
+      out.idx[o] = s_wk[tid];
+      out.log_p[o] = s_ws[tid];
       const double v = rd[q * H + hrow];
-      if (out_adj) out_adj[o] = ndof > 0.0 ? v * ndof / best : (double)NAN;
-      if (out_flags) out_flags[o] = rf[q];
-      if (out_dchi2)
-        for (int h = 0; h < H; ++h) out_dchi2[o * H + h] = rd[q * H + h];
+      if (out.dchi2_adj) out.dchi2_adj[o] = ndof > 0.0 ? v * ndof / best : (double)NAN;
+      if (out.flags) out.flags[o] = rf[q];
+      if (out.dchi2)
+        for (int h = 0; h < H; ++h) out.dchi2[o * H + h] = rd[q * H + h];
     } else {
-      out_idx[o] = -1;
-      out_logp[o] = (double)NAN;
-      if (out_adj) out_adj[o] = (double)NAN;
-      if (out_flags) out_flags[o] = 0;
-      if (out_dchi2)
-        for (int h = 0; h < H; ++h) out_dchi2[o * H + h] = (double)NAN;
+      out.idx[o] = -1;
+      out.log_p[o] = (double)NAN;
+      if (out.dchi2_adj) out.dchi2_adj[o] = (double)NAN;
+      if (out.flags) out.flags[o] = 0;
+      if (out.dchi2)
+        for (int h = 0; h < H; ++h) out.dchi2[o * H + h] = (double)NAN;
     }
   }
 }
@@ -293,27 +365,42 @@ hipError_t solve_top_h(bool fp64, const void* zc, const void* D, const Moments* 
 
 int top_blocks(int64_t n_freq) { return (int)((n_freq + kOwn - 1) / kOwn); }
 
+namespace {
+int top_groups(int64_t n_freq) { return (top_blocks(n_freq) + kNT - 1) / kNT; }
+size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+}  // namespace
+
 size_t top_scratch_bytes(int64_t n_freq, int H, int n_curves, int K) {
   const size_t rec = (size_t)top_blocks(n_freq) * (size_t)n_curves;
-  auto a = [](size_t v) { return (v + 255) & ~(size_t)255; };
-  return a(rec * K * sizeof(double)) + a(rec * K * sizeof(int64_t)) + a(rec * K) +
-         a(rec * K * H * sizeof(double)) + a(rec * sizeof(double));
+  const size_t grp = (size_t)top_groups(n_freq) * (size_t)n_curves;
+  return a256(rec * K * sizeof(double)) + a256(rec * K * sizeof(int64_t)) + a256(rec * K) +
+         a256(rec * K * H * sizeof(double)) + a256(rec * sizeof(double)) +
+         a256(grp * K * sizeof(double)) + 2 * a256(grp * K * sizeof(int64_t)) +
+         a256(grp * sizeof(double));
 }
 
 TopScratch top_scratch_carve(void* base, int64_t n_freq, int H, int n_curves, int K) {
   const size_t rec = (size_t)top_blocks(n_freq) * (size_t)n_curves;
-  auto a = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t grp = (size_t)top_groups(n_freq) * (size_t)n_curves;
   char* p = (char*)base;
   TopScratch s;
   s.score = (double*)p;
-  p += a(rec * K * sizeof(double));
+  p += a256(rec * K * sizeof(double));
   s.k = (int64_t*)p;
-  p += a(rec * K * sizeof(int64_t));
+  p += a256(rec * K * sizeof(int64_t));
   s.flag = (uint8_t*)p;
-  p += a(rec * K);
+  p += a256(rec * K);
   s.d = (double*)p;
-  p += a(rec * K * H * sizeof(double));
+  p += a256(rec * K * H * sizeof(double));
   s.bmax = (double*)p;
+  p += a256(rec * sizeof(double));
+  s.g_score = (double*)p;
+  p += a256(grp * K * sizeof(double));
+  s.g_k = (int64_t*)p;
+  p += a256(grp * K * sizeof(int64_t));
+  s.g_q = (int64_t*)p;
+  p += a256(grp * K * sizeof(int64_t));
+  s.g_max = (double*)p;
   return s;
 }
 
@@ -341,11 +428,19 @@ hipError_t launch_top_merge(const Moments* mom, const Geom& g, int curve0, int n
                             int hrow, int K, const TopScratch& sc, const TopOut& out,
                             hipStream_t st) {
   const int nblk = top_blocks(g.n_freq);
-  hipLaunchKernelGGL(k_top_merge, dim3((unsigned)n_curves), dim3(kNT), (size_t)nblk, st,
-                     (const double*)sc.score, (const int64_t*)sc.k, (const uint8_t*)sc.flag,
-                     (const double*)sc.d, (const double*)sc.bmax, mom, curve0, nblk, K, g.H, hrow,
-                     out.idx, out.log_p, out.dchi2, out.dchi2_adj, out.flags, out.chi2_best,
-                     out.curve_flags);
+  const int ng = top_groups(g.n_freq);
+  // Groups of up to 256 per-block lists, then the group lists of each curve.
+  hipLaunchKernelGGL(k_top_merge, dim3((unsigned)ng, (unsigned)n_curves), dim3(kNT), 0, st,
+                     (const double*)sc.score, (const int64_t*)sc.k, (const int64_t*)nullptr,
+                     (const double*)sc.bmax, nblk, K, sc.g_score, sc.g_k, sc.g_q, sc.g_max, 0,
+                     mom, curve0, g.H, hrow, (const uint8_t*)sc.flag, (const double*)sc.d, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_top_merge, dim3(1u, (unsigned)n_curves), dim3(kNT), 0, st,
+                     (const double*)sc.g_score, (const int64_t*)sc.g_k, (const int64_t*)sc.g_q,
+                     (const double*)sc.g_max, ng, K, (double*)nullptr, (int64_t*)nullptr,
+                     (int64_t*)nullptr, (double*)nullptr, 1, mom, curve0, g.H, hrow,
+                     (const uint8_t*)sc.flag, (const double*)sc.d, out);
   return hipGetLastError();
 }
 
