@@ -185,6 +185,58 @@ def batched_vs_plain(steps):
             "top16_bytes": int(sum(v.numel() * v.element_size() for v in top.values()))}
 
 
+def multi_vs_curves(steps):
+    """Shared-alpha search of the multi workload vs the same sources run as
+    ordinary curves (t replicated, errors scaled) through the batched search."""
+    import torch
+    from paper_0901_1913_amd import fchi2 as F
+    from paper_0901_1913_amd import synth
+    src = synth.make("multi")
+    S, n = src.n_sources, src.t.shape[0]
+    units = S * src.n_freq * src.H
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    plan = F.Plan(src.offsets, src.f_max, src.H, src.n_freq, precision=src.precision)
+    t = torch.from_numpy(src.t).cuda()
+    sg = torch.from_numpy(src.sigma).cuda()
+    x = torch.from_numpy(np.ascontiguousarray(src.x)).cuda()
+    sc = torch.from_numpy(src.scale).cuda()
+    plan.search_multi(t, sg, x, sc)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.search_multi(t, sg, x, sc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_m = e0.elapsed_time(e1) / steps
+    plan.close()
+    off = np.arange(S + 1, dtype=np.int64) * n
+    plan = F.Plan(off, src.f_max, src.H, src.n_freq, precision=src.precision, graph=True)
+    tt = torch.from_numpy(np.tile(src.t, S)).cuda()
+    ss = torch.from_numpy((src.scale[:, None] * src.sigma[None, :]).reshape(-1)).cuda()
+    xx = x.reshape(-1)
+    schedule = plan.autotune(tt, xx, ss)
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        d, c0, _ = plan.search(tt, xx, ss, want_flags=False, stream=side)
+        e0.record(side)
+        for _ in range(steps):
+            plan.search(tt, xx, ss, dchi2=d, chi2_0=c0, want_flags=False, stream=side)
+        e1.record(side)
+        side.synchronize()
+    ms_c = e0.elapsed_time(e1) / steps
+    plan.close()
+    log(f"multi: shared alpha {ms_m:.3f} ms, as curves {ms_c:.3f} ms")
+    return {"workload": "multi", "n_sources": S, "n": n, "H": src.H, "n_freq": src.n_freq,
+            "precision": src.precision, "shared_alpha_ms": round(ms_m, 4),
+            "shared_alpha_value": round(units / (ms_m * 1e-3), 1),
+            "as_curves_ms": round(ms_c, 4), "as_curves_value": round(units / (ms_c * 1e-3), 1),
+            "as_curves_schedule": schedule, "speedup": round(ms_c / ms_m, 3),
+            "unit": "freq*H/s"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +249,8 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-survey vs plain-loop comparison")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--no-multi", action="store_true",
+                    help="skip the shared-alpha multi-source comparison")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device copy of this many MiB (a known-size kernel "
                          "against which HBM counters are scaled)")
@@ -337,6 +391,8 @@ def main(argv=None):
     del dchi2, ws
     if not a.no_batched:
         out["batched"] = batched_vs_plain(a.batched_steps)
+    if not a.no_multi:
+        out["multi"] = multi_vs_curves(a.batched_steps)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -93,7 +93,12 @@ typedef struct {
   int32_t precision;         /* fchi2_precision_t                             */
   uint32_t flags;            /* FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH         */
   int32_t kernel_width;      /* spreading kernel taps, 0 = default
-                                (14 for FP64, 8 for MIXED); 4..16             */
+                                (14 for FP64, 10 for MIXED); 4..16; or 1 =
+                                floor gridding as printed in Section 3b (each
+                                time replaced by the start of its cell of
+                                width 1/(4 n_freq df), no kernel, no
+                                deconvolution; reproduces the paper's
+                                sensitivity loss; no backward)                */
   int32_t curves_per_wave;   /* curves transformed together; 0 = automatic   */
 } fchi2_plan_desc_t;
 
@@ -299,6 +304,26 @@ fchi2_status_t fchi2_search_multi(fchi2_plan_t plan, const double* t, const doub
                                   const double* x, const double* scale, int32_t n_sources,
                                   void* workspace, size_t workspace_bytes, void* dchi2,
                                   double* chi2_0, uint8_t* flags, void* stream);
+
+/*
+ * Polynomial detrending (the option of the paper's reference implementation
+ * described in Section 4: remove a slow polynomial variation, up to t^3,
+ * before searching for periodic variation on top of it).  For every curve of
+ * the plan, subtracts the weighted least-squares polynomial of the given
+ * degree in t (minimising sum (x - p(t))^2 / sigma^2) and writes the
+ * residuals; search them with any other entry point.  The fit is taken in
+ * Legendre polynomials of u = 2 (t - T0) / span - 1 (T0 and span from the
+ * first and last time of the curve), Cholesky in FP64; a pivot below 1e-12
+ * of its diagonal is dropped (fewer than degree + 1 distinct times).
+ *  degree  0..3 (0: subtract the weighted mean)
+ *  x_out   device FP64 [n_total]; may be x itself (in place)
+ *  coef    device FP64 [n_curves][degree + 1] Legendre coefficients, or NULL
+ * Non-finite inputs propagate NaN to the curve's residuals.
+ * Errors: FCHI2_ERR_ARG (NULL, degree), FCHI2_ERR_HIP.
+ */
+fchi2_status_t fchi2_detrend(fchi2_plan_t plan, const double* t, const double* x,
+                             const double* sigma, int32_t degree, double* x_out, double* coef,
+                             void* stream);
 
 /*
  * Measurement support.  fchi2_profile(plan, 1) makes every later

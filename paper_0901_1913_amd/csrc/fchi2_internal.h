@@ -21,8 +21,9 @@ struct Moments {
   double chi2_0;  // chi2 of the constant model
   double T0;      // epoch: first (smallest) time
   double span;    // last minus first time
-  int64_t start;  // CSR offset of the curve
+  int64_t start;  // CSR offset of the curve (of its t and sigma)
   int64_t n;      // number of points
+  int64_t xshift; // x of point i is x[i + xshift] (nonzero for sources sharing t)
   uint32_t flags; // CF_* bits
   uint32_t pad;
 };

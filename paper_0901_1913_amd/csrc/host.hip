@@ -544,8 +544,10 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     return fail(FCHI2_ERR_ARG, "precision must be FCHI2_FP64 or FCHI2_MIXED");
   if (d.flags & ~(uint32_t)(FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH))
     return fail(FCHI2_ERR_ARG, "unknown flag bits 0x%x", d.flags);
-  if (d.kernel_width != 0 && (d.kernel_width < 4 || d.kernel_width > 16))
-    return fail(FCHI2_ERR_ARG, "kernel_width must be 0 or 4..16");
+  if (d.kernel_width != 0 && d.kernel_width != 1 && (d.kernel_width < 4 || d.kernel_width > 16))
+    return fail(FCHI2_ERR_ARG, "kernel_width must be 0, 1 (floor gridding) or 4..16");
+  if (d.kernel_width == 1 && (d.flags & FCHI2_KEEP_FOR_BACKWARD))
+    return fail(FCHI2_ERR_UNSUPPORTED, "floor gridding has no backward");
   if (d.curves_per_wave < 0) return fail(FCHI2_ERR_ARG, "curves_per_wave must be >= 0");
 
   fchi2_plan_s* pl = new fchi2_plan_s();
@@ -565,7 +567,7 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   g.w = d.kernel_width ? d.kernel_width : (pl->fp64 ? 14 : 10);
   g.half_w = 0.5 * g.w;
   g.beta = 2.30 * g.w;
-  g.c_off = g.w / 2 + 2;
+  g.c_off = g.w == 1 ? 0 : g.w / 2 + 2;
   g.H = d.H;
   g.P = d.H + (d.H + 1) / 2;
   std::memset(g.comp_m, 0, sizeof g.comp_m);
@@ -950,6 +952,20 @@ fchi2_status_t fchi2_search_multi(fchi2_plan_t plan, const double* t, const doub
   plan->last_ws = nullptr;  // no backward for this form
   return enqueue_multi(plan, m, t, sigma, x, scale, n_sources, (char*)workspace, dchi2, chi2_0,
                        flags, (hipStream_t)stream);
+}
+
+fchi2_status_t fchi2_detrend(fchi2_plan_t plan, const double* t, const double* x,
+                             const double* sigma, int32_t degree, double* x_out, double* coef,
+                             void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
+  if (!t || !x || !sigma || !x_out)
+    return fail(FCHI2_ERR_ARG, "t, x, sigma and x_out must not be NULL");
+  if (degree < 0 || degree > 3) return fail(FCHI2_ERR_ARG, "degree must be in 0..3");
+  hipError_t e = launch_detrend(t, x, sigma, plan->d_off, plan->desc.n_curves, degree, x_out,
+                                coef, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "detrend");
+  return FCHI2_OK;
 }
 
 fchi2_status_t fchi2_profile(fchi2_plan_t plan, int32_t enable) {

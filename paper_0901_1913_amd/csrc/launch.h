@@ -118,6 +118,12 @@ hipError_t launch_top_merge(const Moments* mom, const Geom& g, int curve0, int n
                             int hrow, int K, const TopScratch& sc, const TopOut& out,
                             hipStream_t st);
 
+// Subtract each curve's weighted least-squares polynomial of the given degree
+// (0..3) in t; coef (nullable) receives its Legendre coefficients in u.
+hipError_t launch_detrend(const double* t, const double* x, const double* sigma,
+                          const int64_t* offsets, int n_curves, int degree, double* x_out,
+                          double* coef, hipStream_t st);
+
 // Fine search on the ungridded points around given centre frequencies.
 struct FineOut {
   double* rows;        // [curve][K][R][H] or null

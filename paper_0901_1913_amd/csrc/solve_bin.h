@@ -151,6 +151,111 @@ __device__ __forceinline__ void prefix_solve(const double* Qr, const double* Qi,
   });
 }
 
+// Shared-alpha form (many sources observed at the same times with errors
+// proportional to one sigma, Section 5): alpha depends on the times and the
+// shared weights only, so it is factored once per bin and reused for every
+// source's beta.  factor_alpha computes L (alpha = L L^T) with the pivot guard;
+// solve_beta then gives Delta chi2(H') = sum_{j <= 2H'} z_j^2 * inv_scale2.
+template <int H>
+__device__ __forceinline__ void factor_alpha(const double* Qr, const double* Qi, double eps,
+                                             uint8_t& fl, double (&Lm)[2 * H + 1][2 * H + 1],
+                                             double (&inv)[2 * H + 1]) {
+  constexpr int dd = 2 * H + 1;
+  static_for<0, dd>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    static_for<0, i + 1>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      double s = alpha_ij(i, j, Qr, Qi);
+      static_for<0, j>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        s -= Lm[i][l] * Lm[j][l];
+      });
+      if constexpr (i == j) {
+        const double ajj = alpha_ij(i, i, Qr, Qi);
+        if (s > eps * ajj && s > 0.0) {
+          const double r = sqrt(s);
+          Lm[i][i] = r;
+          inv[i] = 1.0 / r;
+        } else {
+          Lm[i][i] = 0.0;
+          inv[i] = 0.0;
+          fl |= BF_PIVOT;
+        }
+      } else {
+        Lm[i][j] = s * inv[j];
+      }
+    });
+  });
+}
+
+template <int H, typename O>
+__device__ __forceinline__ void solve_beta(const double (&Lm)[2 * H + 1][2 * H + 1],
+                                           const double (&inv)[2 * H + 1], const double* Pr,
+                                           const double* Pi, double inv_scale2, O* d) {
+  constexpr int dd = 2 * H + 1;
+  double z[dd];
+  double acc = 0.0;
+  static_for<0, dd>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    double s = beta_i(i, Pr, Pi);
+    static_for<0, i>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      s -= Lm[i][l] * z[l];
+    });
+    z[i] = s * inv[i];
+    acc += z[i] * z[i];
+    if constexpr (i >= 2 && (i & 1) == 0) d[i / 2 - 1] = (O)(acc * inv_scale2);
+  });
+}
+
+// Unpack the weight pairs (q_{2p+1}, q_{2p+2}), p < H, of one grid slot.
+template <int H, typename R>
+__device__ __forceinline__ void load_q(const cplx<R>* __restrict__ zc, int64_t nf,
+                                       int64_t base_pair, int64_t k, cplx<double> Dk_, double W,
+                                       double* Qr, double* Qi) {
+  const double Dr = (double)Dk_.x, Di = (double)Dk_.y;
+  Qr[0] = W;
+  Qi[0] = 0.0;
+#pragma unroll
+  for (int pp = 0; pp < H; ++pp) {
+    const cplx<R> z0 = zc[((base_pair + pp) * 2 + 0) * nf + k];
+    const cplx<R> z1 = zc[((base_pair + pp) * 2 + 1) * nf + k];
+    const double ax = 0.5 * ((double)z0.x + (double)z1.x);
+    const double ay = 0.5 * ((double)z0.y - (double)z1.y);
+    const double bx = 0.5 * ((double)z0.y + (double)z1.y);
+    const double by = -0.5 * ((double)z0.x - (double)z1.x);
+    Qr[2 * pp + 1] = ax * Dr - ay * Di;
+    Qi[2 * pp + 1] = ax * Di + ay * Dr;
+    Qr[2 * pp + 2] = bx * Dr - by * Di;
+    Qi[2 * pp + 2] = bx * Di + by * Dr;
+  }
+}
+
+// Unpack the data pairs (p_{2j+1}, p_{2j+2}), j < ceil(H/2), of one grid slot.
+template <int H, typename R>
+__device__ __forceinline__ void load_p(const cplx<R>* __restrict__ zc, int64_t nf,
+                                       int64_t base_pair, int64_t k, cplx<double> Dk_,
+                                       double* Pr, double* Pi) {
+  const double Dr = (double)Dk_.x, Di = (double)Dk_.y;
+  Pr[0] = 0.0;
+  Pi[0] = 0.0;
+#pragma unroll
+  for (int j = 0; j < (H + 1) / 2; ++j) {
+    const cplx<R> z0 = zc[((base_pair + j) * 2 + 0) * nf + k];
+    const cplx<R> z1 = zc[((base_pair + j) * 2 + 1) * nf + k];
+    const double ax = 0.5 * ((double)z0.x + (double)z1.x);
+    const double ay = 0.5 * ((double)z0.y - (double)z1.y);
+    const double bx = 0.5 * ((double)z0.y + (double)z1.y);
+    const double by = -0.5 * ((double)z0.x - (double)z1.x);
+    Pr[2 * j + 1] = ax * Dr - ay * Di;
+    Pi[2 * j + 1] = ax * Di + ay * Dr;
+    if (2 * j + 2 <= H) {
+      Pr[2 * j + 2] = bx * Dr - by * Di;
+      Pi[2 * j + 2] = bx * Di + by * Dr;
+    }
+  }
+}
+
 // Delta chi2 of bin k of curve c (wave slot cw) for H' = 1..H, rounded to the
 // output type, into d[0..H-1]; returns the bin's flags.  Curves with a fatal
 // data flag give NaN rows; k = 0 gives zero rows and the DC flag.

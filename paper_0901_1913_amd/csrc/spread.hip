@@ -44,18 +44,22 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
 }
 
 // Phase 1: block b of curve c reduces a contiguous chunk of the curve to
-// (W_b, mean_b, M2_b = sum w (x - mean_b)^2) and validity bits.
+// (W_b, mean_b, M2_b = sum w (x - mean_b)^2) and validity bits.  With
+// shared_t every curve c uses the points [off[0], off[1]) of t and sigma and
+// its own data x[c * n + i] (sources observed at the same times).
 __global__ __launch_bounds__(kNT) void k_moments_part(const double* __restrict__ t,
                                                       const double* __restrict__ x,
                                                       const double* __restrict__ sigma,
                                                       const int64_t* __restrict__ off,
-                                                      int bpc, MomPart* __restrict__ part) {
+                                                      int bpc, int shared_t,
+                                                      MomPart* __restrict__ part) {
   __shared__ double red[kNT];
   __shared__ uint32_t bad_s;
   const int c = blockIdx.y;
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
-  const int64_t a = off[c], e = off[c + 1];
+  const int64_t a = shared_t ? off[0] : off[c], e = shared_t ? off[1] : off[c + 1];
+  const int64_t xs = shared_t ? (int64_t)c * (e - a) : 0;
   const int64_t n = e - a;
   const int64_t chunk = (n + bpc - 1) / bpc;
   const int64_t lo = a + (int64_t)b * chunk;
@@ -65,7 +69,7 @@ __global__ __launch_bounds__(kNT) void k_moments_part(const double* __restrict__
   double sw = 0.0, swx = 0.0;
   uint32_t bad = 0;
   for (int64_t i = lo + tid; i < hi; i += kNT) {
-    const double ti = t[i], xi = x[i], si = sigma[i];
+    const double ti = t[i], xi = x[i + xs], si = sigma[i];
     if (!isfinite(ti) || !isfinite(xi) || !isfinite(si) || !(si > 0.0)) bad |= CF_NONFINITE;
     if (i > a && !(ti >= t[i - 1])) bad |= CF_UNSORTED;
     const double w = 1.0 / (si * si);
@@ -79,7 +83,7 @@ __global__ __launch_bounds__(kNT) void k_moments_part(const double* __restrict__
   double sc = 0.0;
   for (int64_t i = lo + tid; i < hi; i += kNT) {
     const double si = sigma[i];
-    const double y = x[i] - mean;
+    const double y = x[i + xs] - mean;
     sc += y * y / (si * si);
   }
   const double M2 = block_sum(sc, red);
@@ -98,13 +102,14 @@ __global__ __launch_bounds__(kNT) void k_moments_part(const double* __restrict__
 // variance update) and writes the curve's Moments and chi2_0.
 __global__ __launch_bounds__(kNT) void k_moments_fin(const double* __restrict__ t,
                                                      const int64_t* __restrict__ off,
-                                                     int n_curves, int bpc,
+                                                     int n_curves, int bpc, int shared_t,
+                                                     const double* __restrict__ scale,
                                                      const MomPart* __restrict__ part, Geom g,
                                                      Moments* __restrict__ mom,
                                                      double* __restrict__ chi2_out) {
   const int c = blockIdx.x * kNT + threadIdx.x;
   if (c >= n_curves) return;
-  const int64_t a = off[c], e = off[c + 1];
+  const int64_t a = shared_t ? off[0] : off[c], e = shared_t ? off[1] : off[c + 1];
   const int64_t n = e - a;
   double W = 0.0, mean = 0.0, M2 = 0.0;
   uint32_t fl = 0;
@@ -124,6 +129,7 @@ __global__ __launch_bounds__(kNT) void k_moments_fin(const double* __restrict__ 
   m.chi2_0 = M2;
   m.start = a;
   m.n = n;
+  m.xshift = shared_t ? (int64_t)c * n : 0;
   if (n <= 0) {
     fl |= CF_EMPTY;
     m.T0 = 0.0;
@@ -138,16 +144,29 @@ __global__ __launch_bounds__(kNT) void k_moments_fin(const double* __restrict__ 
     const double pos = ((double)(2 * g.H) * v) * (double)g.L + (double)g.c_off;
     if (!(pos + (double)(g.w / 2) + 3.0 <= (double)g.L)) fl |= CF_WRAP;
   }
+  // A source whose errors are scale[c] times the shared sigma: its chi2 is the
+  // base-weight sum divided by scale^2 (the weights are sigma^-2 / scale^2).
+  double sc2 = 1.0;
+  if (scale) {
+    const double sv = scale[c];
+    if (!(sv > 0.0) || !isfinite(sv)) fl |= CF_NONFINITE;
+    sc2 = sv * sv;
+  }
   m.flags = fl;
   m.pad = 0;
   mom[c] = m;
-  if (chi2_out) chi2_out[c] = (fl & kCurveFatal) ? NAN : M2;
+  if (chi2_out) chi2_out[c] = (fl & kCurveFatal) ? NAN : M2 / sc2;
 }
 
 // Cell coordinate of point i for harmonic multiple m (FP64 phase reduction).
+// Floor gridding (kernel width 1, Section 3b): the point's time is replaced by
+// the start of its cell, floor(v L), and harmonic m sits at m times that cell
+// (an exact integer); the kernel weight is then 1 at that cell only.
 __device__ __forceinline__ double cell_pos(const double* __restrict__ t, int64_t i, double T0,
-                                           double df, int m, double L, double c_off) {
+                                           double df, int m, double L, double c_off,
+                                           bool flr) {
   const double v = (t[i] - T0) * df;
+  if (flr) return (double)m * floor(v * L);
   return ((double)m * v) * L + c_off;
 }
 
@@ -163,7 +182,7 @@ __device__ __forceinline__ double cell_pos(const double* __restrict__ t, int64_t
 __device__ __forceinline__ int64_t tile_limit(const double* __restrict__ t, const Moments& mo,
                                               const Geom& g, int m, int log_tile) {
   const double last = cell_pos(t, mo.start + mo.n - 1, mo.T0, g.df, m, (double)g.L,
-                               (double)g.c_off);
+                               (double)g.c_off, g.w == 1);
   return (int64_t)floor((last + (double)(g.w / 2 + 2)) / (double)((int64_t)1 << log_tile)) + 3;
 }
 
@@ -184,13 +203,13 @@ __global__ __launch_bounds__(kNT) void k_tile_bounds(const double* __restrict__ 
   if (il == 0) {
     t_min = 0;
   } else {
-    const double lo = cell_pos(t, mo.start + il - 1, mo.T0, g.df, m, Ld, coff);
+    const double lo = cell_pos(t, mo.start + il - 1, mo.T0, g.df, m, Ld, coff, g.w == 1);
     t_min = (int64_t)floor((lo + shift) / B) + 1;
   }
   if (il == mo.n) {
     t_max = tile_limit(t, mo, g, m, log_tile);
   } else {
-    const double hi = cell_pos(t, mo.start + il, mo.T0, g.df, m, Ld, coff);
+    const double hi = cell_pos(t, mo.start + il, mo.T0, g.df, m, Ld, coff, g.w == 1);
     t_max = (int64_t)floor((hi + shift) / B);
   }
   if (t_min < 0) t_min = 0;
@@ -224,7 +243,8 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
                                                 const double* __restrict__ sigma,
                                                 const Moments* __restrict__ mom, Geom g,
                                                 int curve0, const int32_t* __restrict__ tb,
-                                                int ntb, cplx<S>* __restrict__ grid) {
+                                                int ntb, int share_tb,
+                                                cplx<S>* __restrict__ grid) {
   constexpr bool EXACT = sizeof(S) == 8;
   constexpr int B = 1 << LOGB;
   constexpr int CPT = B / kNT;
@@ -267,18 +287,20 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
     const int kind_b = both ? g.comp_kind[p][1] : -1;
     // No point of harmonic m reaches tiles past tile_limit - 2.
     if ((int64_t)blockIdx.x + 2 > tile_limit(t, mo, g, m, LOGB)) continue;
-    const int32_t* row = tb + ((int64_t)cw * (2 * g.H) + (m - 1)) * ntb;
+    const int32_t* row = tb + ((int64_t)(share_tb ? 0 : cw) * (2 * g.H) + (m - 1)) * ntb;
     const int64_t i_lo = pa + row[blockIdx.x], i_hi = pa + row[blockIdx.x + 2];
 
     for (int64_t ch = i_lo; ch < i_hi; ch += CH) {
       const int cnt = (int)((i_hi - ch) < CH ? (i_hi - ch) : CH);
       for (int q = tid; q < cnt; q += kNT) {
         const int64_t i = ch + q;
-        const double pos = cell_pos(t, i, mo.T0, g.df, m, Ld, coff);
+        // floor gridding: pos is an integer, fr = 0 and the kernel below is
+        // exp(0) = 1 at d = 0 and 0 at |d| >= 1 (w = 1)
+        const double pos = cell_pos(t, i, mo.T0, g.df, m, Ld, coff, g.w == 1);
         const double fl = floor(pos);
         const double si = sigma[i];
         const double w = 1.0 / (si * si);
-        const double wy = w * (x[i] - mo.xbar);
+        const double wy = w * (x[i + mo.xshift] - mo.xbar);
         const double sa = (kind_a == 0) ? w : wy;
         double sre, sim;
         if (comp == 0) {
@@ -339,6 +361,10 @@ __global__ __launch_bounds__(kNT) void k_deconv(cplx<double>* __restrict__ D, Ge
                                                 const double* __restrict__ gw, int ng) {
   const int64_t k = (int64_t)blockIdx.x * kNT + threadIdx.x;
   if (k >= g.n_freq) return;
+  if (g.w == 1) {  // floor gridding: no kernel to divide out, no origin shift
+    D[k] = cmk<double>(1.0, 0.0);
+    return;
+  }
   // phi_hat(k) = w * int_0^1 phi(z) cos(pi w k z / L) dz, phi(z) folded into gw.
   const double a = M_PI * (double)g.w * (double)k / (double)g.L;
   double s = 0.0;
@@ -355,40 +381,45 @@ __global__ __launch_bounds__(kNT) void k_deconv(cplx<double>* __restrict__ D, Ge
 
 hipError_t launch_moments(const double* t, const double* x, const double* sigma,
                           const int64_t* offsets, int n_curves, int bpc, const Geom& g,
-                          MomPart* part, Moments* mom, double* chi2_0, hipStream_t st) {
+                          MomPart* part, Moments* mom, double* chi2_0, hipStream_t st,
+                          bool shared_t, const double* scale) {
   hipLaunchKernelGGL(k_moments_part, dim3(bpc, n_curves), dim3(kNT), 0, st, t, x, sigma,
-                     offsets, bpc, part);
+                     offsets, bpc, shared_t ? 1 : 0, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_moments_fin, dim3((n_curves + kNT - 1) / kNT), dim3(kNT), 0, st, t,
-                     offsets, n_curves, bpc, part, g, mom, chi2_0);
+                     offsets, n_curves, bpc, shared_t ? 1 : 0, scale, part, g, mom, chi2_0);
   return hipGetLastError();
 }
 
 hipError_t launch_spread(bool fp64, const double* t, const double* x, const double* sigma,
                          const Moments* mom, const Geom& g, int curve0, int n_curves,
-                         int64_t max_n, int32_t* tb, void* grid, int log_tile, hipStream_t st) {
+                         int64_t max_n, int32_t* tb, void* grid, int log_tile, hipStream_t st,
+                         bool share_tb) {
   const int64_t tiles = g.L >> log_tile;
   const int ntb = (int)tiles + 2;
   dim3 gb((unsigned)((max_n + 1 + kNT - 1) / kNT), (unsigned)(2 * g.H), (unsigned)n_curves);
-  hipLaunchKernelGGL(k_tile_bounds, gb, dim3(kNT), 0, st, t, mom, g, curve0, log_tile, ntb, tb);
+  // Sources sharing one time base share the table of slot 0 (built already).
+  if (!share_tb)
+    hipLaunchKernelGGL(k_tile_bounds, gb, dim3(kNT), 0, st, t, mom, g, curve0, log_tile, ntb,
+                       tb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   dim3 gr((unsigned)tiles, (unsigned)g.P, (unsigned)n_curves);
   if (log_tile == 10) {
     if (fp64)
       hipLaunchKernelGGL((k_spread<double, 10>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
-                         curve0, tb, ntb, (cplx<double>*)grid);
+                         curve0, tb, ntb, share_tb ? 1 : 0, (cplx<double>*)grid);
     else
       hipLaunchKernelGGL((k_spread<float, 10>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
-                         curve0, tb, ntb, (cplx<float>*)grid);
+                         curve0, tb, ntb, share_tb ? 1 : 0, (cplx<float>*)grid);
   } else if (log_tile == 11) {
     if (fp64)
       hipLaunchKernelGGL((k_spread<double, 11>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
-                         curve0, tb, ntb, (cplx<double>*)grid);
+                         curve0, tb, ntb, share_tb ? 1 : 0, (cplx<double>*)grid);
     else
       hipLaunchKernelGGL((k_spread<float, 11>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
-                         curve0, tb, ntb, (cplx<float>*)grid);
+                         curve0, tb, ntb, share_tb ? 1 : 0, (cplx<float>*)grid);
   } else {
     return hipErrorInvalidValue;
   }

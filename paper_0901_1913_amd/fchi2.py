@@ -32,6 +32,7 @@ EXPORTS = (
     "fchi2_profile_read", "fchi2_autotune", "fchi2_plan_info",
     "fchi2_search_top_workspace_bytes", "fchi2_search_top",
     "fchi2_fine_scratch_bytes", "fchi2_fine_search",
+    "fchi2_search_multi_workspace_bytes", "fchi2_search_multi", "fchi2_detrend",
 )
 PROF_STAGES = ("moments", "spread", "fft_first", "fft_mid", "fft_last", "solve",
                "bwd_solve", "bwd_fft", "bwd_gather", "bwd_final", "top_merge",
@@ -134,6 +135,12 @@ def lib() -> ctypes.CDLL:
     L.fchi2_fine_search.argtypes = [vp, vp, vp, vp, vp, i32, i32, ctypes.c_double, i32, vp, sz,
                                     ctypes.POINTER(FineOut), vp]
     L.fchi2_fine_search.restype = ctypes.c_int
+    L.fchi2_search_multi_workspace_bytes.argtypes = [vp, i32]
+    L.fchi2_search_multi_workspace_bytes.restype = sz
+    L.fchi2_search_multi.argtypes = [vp, vp, vp, vp, vp, i32, vp, sz, vp, vp, vp, vp]
+    L.fchi2_search_multi.restype = ctypes.c_int
+    L.fchi2_detrend.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+    L.fchi2_detrend.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -303,6 +310,56 @@ class Plan:
             ctypes.c_void_p(res["chi2_0"].data_ptr()), ctypes.byref(out),
             ctypes.c_void_p(_stream_handle(stream))))
         return res
+
+    def detrend(self, t, x, sigma, degree: int, x_out=None, want_coef=False, stream=None):
+        """Residuals of each curve's weighted least-squares polynomial fit
+        (degree 0..3); returns x_out (and the Legendre coefficients)."""
+        torch = _torch()
+        f64 = torch.float64
+        if x_out is None:
+            x_out = torch.empty_like(x)
+        coef = (torch.empty((self.n_curves, int(degree) + 1), dtype=f64, device=t.device)
+                if want_coef else None)
+        _check(lib().fchi2_detrend(
+            self._h, _dev_ptr(t, f64, self.n_total, "t"), _dev_ptr(x, f64, self.n_total, "x"),
+            _dev_ptr(sigma, f64, self.n_total, "sigma"), int(degree),
+            _dev_ptr(x_out, f64, self.n_total, "x_out"),
+            _dev_ptr(coef, f64, None, "coef") if coef is not None else ctypes.c_void_p(0),
+            ctypes.c_void_p(_stream_handle(stream))))
+        return (x_out, coef) if want_coef else x_out
+
+    def search_multi(self, t, sigma, x, scale, want_flags=True, stream=None):
+        """Shared-alpha search of sources observed at the plan's single time base.
+
+        t, sigma: device FP64 [n]; x: device FP64 [n_sources, n]; scale: device
+        FP64 [n_sources] (source errors are scale * sigma).  Returns
+        (dchi2 [n_sources, H, n_freq], chi2_0 [n_sources], flags [n_freq]).
+        """
+        torch = _torch()
+        f64 = torch.float64
+        if self.n_curves != 1:
+            raise ValueError("search_multi needs a plan of one curve (the shared time base)")
+        if x.dim() != 2 or x.shape[1] != self.n_total:
+            raise ValueError("x must have shape [n_sources, n]")
+        S = int(x.shape[0])
+        dev = t.device
+        nbytes = int(lib().fchi2_search_multi_workspace_bytes(self._h, S))
+        if nbytes == 0:
+            raise FChi2Error(ERR_UNSUPPORTED, "shared-alpha search needs H <= 5")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        dchi2 = torch.empty((S, self.H, self.n_freq), dtype=self.out_dtype, device=dev)
+        chi2_0 = torch.empty(S, dtype=f64, device=dev)
+        flags = torch.empty(self.n_freq, dtype=torch.uint8, device=dev) if want_flags else None
+        _check(lib().fchi2_search_multi(
+            self._h, _dev_ptr(t, f64, self.n_total, "t"),
+            _dev_ptr(sigma, f64, self.n_total, "sigma"), _dev_ptr(x, f64, S * self.n_total, "x"),
+            _dev_ptr(scale, f64, S, "scale"), S, ctypes.c_void_p(ws.data_ptr()),
+            ctypes.c_size_t(nbytes),
+            _dev_ptr(dchi2, self.out_dtype, S * self.H * self.n_freq, "dchi2"),
+            _dev_ptr(chi2_0, f64, S, "chi2_0"),
+            _dev_ptr(flags, torch.uint8, self.n_freq, "flags") if flags is not None
+            else ctypes.c_void_p(0), ctypes.c_void_p(_stream_handle(stream))))
+        return dchi2, chi2_0, flags
 
     def fine_search(self, t, x, sigma, f_center, R: int = 64,
                     half_width: Optional[float] = None, hrow: Optional[int] = None,

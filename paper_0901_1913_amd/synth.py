@@ -21,6 +21,14 @@ the five named workloads:
   stress   one curve, n=1e6 over 1e4 d at t ~ 2.45e6, eight harmonics of
            period 0.1234 d, sigma log-uniform over [1e-3, 1], H=8,
            2^24 bins up to 40 /d (precision stress)
+
+and one for the shared-alpha form (many sources at the same sampling times
+with proportional errors, as an imager revisiting one field, Section 5):
+
+  multi    2000 sources at 400 shared times over 1000 d, shared sigma
+           uniform in [0.01, 0.05], per-source error scale log-uniform in
+           [0.5, 4], a third of the sources with a sinusoid, H=3, 2^16 bins
+           up to 10 /d
 """
 from __future__ import annotations
 
@@ -28,8 +36,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-WORKLOADS = ("plain", "long", "batch", "diff", "stress")
-SEEDS = {"plain": 1, "long": 2, "batch": 3, "diff": 4, "stress": 5}
+WORKLOADS = ("plain", "long", "batch", "diff", "stress", "multi")
+SEEDS = {"plain": 1, "long": 2, "batch": 3, "diff": 4, "stress": 5, "multi": 6}
 
 
 @dataclass
@@ -164,9 +172,57 @@ def batch(seed=3, n_curves=10_000, n_lo=50, n_hi=5000, span_lo=30.0,
                   meta=dict(periods=periods, with_signal=with_signal))
 
 
+@dataclass
+class Sources:
+    """Many sources observed at one set of times with proportional errors."""
+    t: np.ndarray          # float64 [n], ascending
+    sigma: np.ndarray      # float64 [n], shared error shape
+    x: np.ndarray          # float64 [n_sources, n]
+    scale: np.ndarray      # float64 [n_sources]: source s has errors scale[s] * sigma
+    H: int
+    n_freq: int
+    f_max: float
+    precision: str
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_sources(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def offsets(self) -> np.ndarray:
+        return np.array([0, self.t.shape[0]], dtype=np.int64)
+
+    def source(self, s: int):
+        """(t, x, sigma) of source s as an ordinary curve."""
+        return self.t, self.x[s], self.scale[s] * self.sigma
+
+
+def multi(seed=6, n_sources=2000, n=400, span=1000.0, H=3, n_freq=2 ** 16, f_max=10.0,
+          precision="mixed"):
+    """Sources sharing sampling times; a third carry a sinusoid."""
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.uniform(0.0, span, n))
+    sigma = rng.uniform(0.01, 0.05, n)
+    scale = 10.0 ** rng.uniform(np.log10(0.5), np.log10(4.0), n_sources)
+    x = (scale[:, None] * sigma[None, :]) * rng.standard_normal((n_sources, n))
+    x += rng.uniform(-1.0, 1.0, n_sources)[:, None]           # source mean levels
+    periods = np.full(n_sources, np.nan)
+    sig = rng.permutation(n_sources)[: n_sources // 3]
+    for s_ in sig:
+        P = 10.0 ** rng.uniform(-1.0, 1.5)
+        A = rng.uniform(0.02, 0.2) * scale[s_]
+        x[s_] += A * np.sin(2 * np.pi * t / P + rng.uniform(0.0, 2 * np.pi))
+        periods[s_] = P
+    return Sources(t=t, sigma=sigma, x=x, scale=scale, H=H, n_freq=n_freq,
+                   f_max=float(f_max), precision=precision, name="multi",
+                   meta=dict(periods=periods))
+
+
 def make(name, **overrides):
     """Build the named workload; keyword overrides shrink it for tests."""
     fn = {"plain": plain, "long": long, "batch": batch, "diff": diff,
-          "stress": stress}[name]
+          "stress": stress, "multi": multi}[name]
     overrides.setdefault("seed", SEEDS[name])
     return fn(**overrides)

@@ -55,6 +55,7 @@ def _plan(**kw):
     (dict(precision=7), F.ERR_ARG, "precision"),
     (dict(flags=64), F.ERR_ARG, "flag"),
     (dict(kernel_width=3), F.ERR_ARG, "kernel_width"),
+    (dict(kernel_width=2), F.ERR_ARG, "kernel_width"),
     (dict(offsets=[1, 5]), F.ERR_ARG, "offsets[0]"),
     (dict(offsets=[0, 5, 3]), F.ERR_ARG, "nondecreasing"),
     (dict(curves_per_wave=-1), F.ERR_ARG, "curves_per_wave"),
@@ -86,4 +87,8 @@ def test_null_arguments():
     assert L.fchi2_fine_search(None, None, None, None, None, 4, 8, 0.1, 0, None, 0, None,
                                None) == F.ERR_ARG
     assert L.fchi2_fine_scratch_bytes(None, 4, 8) == 0
+    assert L.fchi2_search_multi(None, None, None, None, None, 4, None, 0, None, None, None,
+                                None) == F.ERR_ARG
+    assert L.fchi2_search_multi_workspace_bytes(None, 4) == 0
+    assert L.fchi2_detrend(None, None, None, None, 1, None, None, None) == F.ERR_ARG
     L.fchi2_destroy(None)
