@@ -353,6 +353,24 @@ def main(argv=None):
     signif = {"K": K, "ms_per_step": round(ms_top, 5), "value": round(units / (ms_top * 1e-3), 1),
               "best_bins": top["idx"][0, :4].tolist(),
               "best_log_p": [round(v, 3) for v in top["log_p"][0, :4].tolist()]}
+    # Fine search on the ungridded points around those K candidates (R trials
+    # over +-1 bin, three zoom levels), FP64 direct sums.
+    R = 64
+    fc = torch.where(top["idx"] >= 0, top["idx"].double() * (cur.f_max / cur.n_freq),
+                     torch.full_like(top["log_p"], float("nan")))
+    fine = plan.refine(t, x, s, fc, levels=3, R=R)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(a.steps):
+        fine = plan.refine(t, x, s, fc, levels=3, R=R)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_fine = ev0.elapsed_time(ev1) / a.steps
+    pairs = 3 * K * R * int(cur.t.shape[0])
+    log(f"fine search, 3 levels x {K} x {R}: {ms_fine:.4f} ms")
+    signif["fine"] = {"levels": 3, "R": R, "ms": round(ms_fine, 5),
+                      "point_trials_per_s": round(pairs / (ms_fine * 1e-3), 1),
+                      "f_best": [round(v, 9) for v in fine["f_best"][0, :4].tolist()]}
 
     d_gpu = dchi2.double().cpu().numpy()[0]
     out = {

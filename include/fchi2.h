@@ -355,8 +355,8 @@ fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* 
 /*
  * Autotuner.  Times every candidate schedule of the plan on the caller's data
  * (the FFT digit splits with the fewest passes and the most balanced splits
- * with one pass more, spreading tiles of 1024 or
- * 2048 cells, and waves of wave_max, wave_max/2, wave_max/4 curves) with HIP
+ * with one pass more, spreading tiles of 1024 to
+ * 8192 cells, and waves of wave_max, wave_max/2, wave_max/4 curves) with HIP
  * events on `stream`, keeps the fastest in the plan, and appends it to the
  * text file `cache_path` (may be NULL) keyed by the shape bucket (H, n_freq,
  * precision, kernel width, log2 curves, log2 largest curve, wave_max).  If

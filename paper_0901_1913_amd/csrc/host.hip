@@ -1047,7 +1047,7 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
         int np = 0, ln[kMaxPasses + 1] = {0}, tile = 0, wave = 0;
         if (sscanf(tag, " | np=%d fft=%d,%d,%d,%d tile=%d wave=%d", &np, &ln[1], &ln[2], &ln[3],
                    &ln[4], &tile, &wave) == 7 &&
-            (tile == 10 || tile == 11) && wave >= 1 && wave <= pl->wave_max)
+            tile >= 10 && tile <= 13 && wave >= 1 && wave <= pl->wave_max)
           found = apply(ln, np, tile, wave);
       }
       fclose(fh);
@@ -1068,7 +1068,7 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
   int best_tile = pl->log_tile, best_wave = pl->wave;
   fchi2_status_t res = FCHI2_OK;
   for (const FftPlan& f : splits) {
-    for (int tile : {10, 11}) {
+    for (int tile : {10, 11, 12, 13}) {
       for (int wave : waves) {
         pl->log_tile = tile;
         pl->wave = wave;

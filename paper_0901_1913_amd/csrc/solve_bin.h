@@ -128,9 +128,9 @@ __device__ __forceinline__ void prefix_solve(const double* Qr, const double* Qi,
       if constexpr (i == j) {
         const double ajj = alpha_ij(i, i, Qr, Qi);
         if (s > eps * ajj && s > 0.0) {
-          const double r = sqrt(s);
-          Lm[i][i] = r;
-          inv[i] = 1.0 / r;
+          // only 1/L_ii enters the solve: one reciprocal square root
+          inv[i] = rsqrt(s);
+          Lm[i][i] = s * inv[i];
         } else {
           Lm[i][i] = 0.0;
           inv[i] = 0.0;
@@ -173,9 +173,9 @@ __device__ __forceinline__ void factor_alpha(const double* Qr, const double* Qi,
       if constexpr (i == j) {
         const double ajj = alpha_ij(i, i, Qr, Qi);
         if (s > eps * ajj && s > 0.0) {
-          const double r = sqrt(s);
-          Lm[i][i] = r;
-          inv[i] = 1.0 / r;
+          // only 1/L_ii enters the solve: one reciprocal square root
+          inv[i] = rsqrt(s);
+          Lm[i][i] = s * inv[i];
         } else {
           Lm[i][i] = 0.0;
           inv[i] = 0.0;

@@ -18,7 +18,9 @@
 // each workgroup owns a tile of cells of one packed grid and sums the kernel
 // contributions of its points cell by cell (deterministic, no atomics).  The
 // arithmetic is FP64; the grid is stored as S (float for mixed plans).
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "fchi2_internal.h"
 #include "launch.h"
@@ -256,13 +258,23 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
   __shared__ int s_first[kNT];
 
   const int tid = threadIdx.x;
-  const int p = blockIdx.y;
   const int cw = blockIdx.z;
   const Moments mo = mom[curve0 + cw];
   if (mo.flags & kCurveFatal) return;
-  const int64_t E = pair_extent(mo, g, p);
-  const int64_t a0 = (int64_t)blockIdx.x * B;
-  if (a0 >= E) return;
+  // Work items: the tiles below each pair's nonzero extent, pair after pair
+  // (cells beyond the extent are never read); blocks stride over them.
+  int64_t items = 0;
+  for (int q = 0; q < g.P; ++q) items += pair_extent(mo, g, q) >> LOGB;
+  for (int64_t wi = blockIdx.x; wi < items; wi += gridDim.x) {
+  int p = 0;
+  int64_t tile = wi;
+  for (;;) {
+    const int64_t nt = pair_extent(mo, g, p) >> LOGB;
+    if (tile < nt) break;
+    tile -= nt;
+    ++p;
+  }
+  const int64_t a0 = tile * B;
 
   const int hw = g.w / 2;
   const double two_over_w = 2.0 / (double)g.w;
@@ -286,9 +298,9 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
     const int kind_a = g.comp_kind[p][comp];
     const int kind_b = both ? g.comp_kind[p][1] : -1;
     // No point of harmonic m reaches tiles past tile_limit - 2.
-    if ((int64_t)blockIdx.x + 2 > tile_limit(t, mo, g, m, LOGB)) continue;
+    if (tile + 2 > tile_limit(t, mo, g, m, LOGB)) continue;
     const int32_t* row = tb + ((int64_t)(share_tb ? 0 : cw) * (2 * g.H) + (m - 1)) * ntb;
-    const int64_t i_lo = pa + row[blockIdx.x], i_hi = pa + row[blockIdx.x + 2];
+    const int64_t i_lo = pa + row[tile], i_hi = pa + row[tile + 2];
 
     for (int64_t ch = i_lo; ch < i_hi; ch += CH) {
       const int cnt = (int)((i_hi - ch) < CH ? (i_hi - ch) : CH);
@@ -354,6 +366,7 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
   cplx<S>* out = grid + ((int64_t)cw * g.P + p) * g.L + a0;
 #pragma unroll
   for (int u = 0; u < CPT; ++u) out[tid + u * kNT] = cmk<S>((S)acc_re[u], (S)acc_im[u]);
+  }
 }
 
 __global__ __launch_bounds__(kNT) void k_deconv(cplx<double>* __restrict__ D, Geom g,
@@ -405,23 +418,24 @@ hipError_t launch_spread(bool fp64, const double* t, const double* x, const doub
                        tb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dim3 gr((unsigned)tiles, (unsigned)g.P, (unsigned)n_curves);
-  if (log_tile == 10) {
+  // Blocks stride over the non-empty tiles of each curve (counted on the device).
+  const int64_t cap = std::max<int64_t>(8, 4096 / std::max(n_curves, 1));
+  dim3 gr((unsigned)std::min<int64_t>(cap, tiles * g.P), 1u, (unsigned)n_curves);
+  auto launch = [&](auto logb) -> void {
+    constexpr int LB = decltype(logb)::value;
     if (fp64)
-      hipLaunchKernelGGL((k_spread<double, 10>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
+      hipLaunchKernelGGL((k_spread<double, LB>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
                          curve0, tb, ntb, share_tb ? 1 : 0, (cplx<double>*)grid);
     else
-      hipLaunchKernelGGL((k_spread<float, 10>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
+      hipLaunchKernelGGL((k_spread<float, LB>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
                          curve0, tb, ntb, share_tb ? 1 : 0, (cplx<float>*)grid);
-  } else if (log_tile == 11) {
-    if (fp64)
-      hipLaunchKernelGGL((k_spread<double, 11>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
-                         curve0, tb, ntb, share_tb ? 1 : 0, (cplx<double>*)grid);
-    else
-      hipLaunchKernelGGL((k_spread<float, 11>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
-                         curve0, tb, ntb, share_tb ? 1 : 0, (cplx<float>*)grid);
-  } else {
-    return hipErrorInvalidValue;
+  };
+  switch (log_tile) {
+    case 10: launch(std::integral_constant<int, 10>{}); break;
+    case 11: launch(std::integral_constant<int, 11>{}); break;
+    case 12: launch(std::integral_constant<int, 12>{}); break;
+    case 13: launch(std::integral_constant<int, 13>{}); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
