@@ -41,13 +41,19 @@ def measured_traffic(workload):
     if not m:
         return {}
     meta = json.loads(m.group(1))
-    src = {"fft_first": "fft.hip", "fft_mid": "fft.hip", "fft_last": "fft.hip",
-           "solve": "solve.hip", "spread": "spread.hip"}
+    src = {"fft_first": ["fft.hip"], "fft_mid": ["fft.hip"], "fft_last": ["fft.hip"],
+           "solve": ["solve.hip", "solve_bin.h"], "spread": ["spread.hip"]}
     out = {}
     for st, nbytes in meta.get("bytes_per_launch", {}).items():
-        f = os.path.join(ROOT, "paper_0901_1913_amd", "csrc", src.get(st, ""))
-        ok = os.path.isfile(f) and (hashlib.sha256(open(f, "rb").read()).hexdigest()[:16]
-                                    == meta.get("source_sha256_16", {}).get(st))
+        h = hashlib.sha256()
+        ok = st in src
+        for f in src.get(st, []):
+            path = os.path.join(ROOT, "paper_0901_1913_amd", "csrc", f)
+            if not os.path.isfile(path):
+                ok = False
+                break
+            h.update(open(path, "rb").read())
+        ok = ok and h.hexdigest()[:16] == meta.get("source_sha256_16", {}).get(st)
         out[st] = int(nbytes) if ok else None
     return out
 
@@ -202,6 +208,7 @@ def multi_vs_curves(steps):
     sg = torch.from_numpy(src.sigma).cuda()
     x = torch.from_numpy(np.ascontiguousarray(src.x)).cuda()
     sc = torch.from_numpy(src.scale).cuda()
+    schedule_m = plan.autotune_multi(t, sg, x, sc)
     plan.search_multi(t, sg, x, sc)
     torch.cuda.synchronize()
     e0.record(stream)
@@ -231,6 +238,7 @@ def multi_vs_curves(steps):
     log(f"multi: shared alpha {ms_m:.3f} ms, as curves {ms_c:.3f} ms")
     return {"workload": "multi", "n_sources": S, "n": n, "H": src.H, "n_freq": src.n_freq,
             "precision": src.precision, "shared_alpha_ms": round(ms_m, 4),
+            "shared_alpha_schedule": schedule_m,
             "shared_alpha_value": round(units / (ms_m * 1e-3), 1),
             "as_curves_ms": round(ms_c, 4), "as_curves_value": round(units / (ms_c * 1e-3), 1),
             "as_curves_schedule": schedule, "speedup": round(ms_c / ms_m, 3),
