@@ -300,6 +300,13 @@ fchi2_status_t fchi2_fine_search(fchi2_plan_t plan, const double* t, const doubl
  * Errors: FCHI2_ERR_ARG, FCHI2_ERR_UNSUPPORTED (H > 5), FCHI2_ERR_HIP.
  */
 size_t fchi2_search_multi_workspace_bytes(fchi2_plan_t plan, int32_t n_sources);
+/* The autotuner of fchi2_autotune for this form: times the FFT splits and
+ * spreading tiles on fchi2_search_multi with the caller's data (dchi2 is
+ * scratch) and keeps the fastest in the plan.  Synchronises `stream`. */
+fchi2_status_t fchi2_autotune_multi(fchi2_plan_t plan, const double* t, const double* sigma,
+                                    const double* x, const double* scale, int32_t n_sources,
+                                    void* workspace, size_t workspace_bytes, void* dchi2,
+                                    void* stream);
 fchi2_status_t fchi2_search_multi(fchi2_plan_t plan, const double* t, const double* sigma,
                                   const double* x, const double* scale, int32_t n_sources,
                                   void* workspace, size_t workspace_bytes, void* dchi2,

@@ -504,6 +504,56 @@ fchi2_status_t check_ws(fchi2_plan_s* pl, void* ws, size_t bytes) {
   return FCHI2_OK;
 }
 
+// Time every (FFT split, spreading tile, wave) candidate with `run` (3 runs,
+// the first a warm-up) and return the fastest; the plan is left on the last
+// candidate tried.
+template <typename Run>
+fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
+                         const std::vector<int>& waves, Run run, hipStream_t st, float& best_ms,
+                         FftPlan& best_f, int& best_tile, int& best_wave) {
+  hipEvent_t e0, e1;
+  hipError_t ce = hipEventCreate(&e0);
+  if (ce != hipSuccess) return hip_fail(ce, "hipEventCreate");
+  ce = hipEventCreate(&e1);
+  if (ce != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(ce, "hipEventCreate");
+  }
+  fchi2_status_t res = FCHI2_OK;
+  for (const FftPlan& f : splits) {
+    for (int tile : {10, 11, 12, 13}) {
+      for (int wave : waves) {
+        pl->log_tile = tile;
+        pl->wave = wave;
+        apply_fft_plan(pl, f);
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3 && res == FCHI2_OK; ++rep) {
+          hipError_t e = hipEventRecord(e0, st);
+          if (e == hipSuccess) res = run();
+          if (e == hipSuccess && res == FCHI2_OK) e = hipEventRecord(e1, st);
+          if (e == hipSuccess && res == FCHI2_OK) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess && res == FCHI2_OK) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) res = hip_fail(e, "autotune timing");
+          if (rep > 0 && ms < ms_min) ms_min = ms;  // first run warms up
+        }
+        if (res != FCHI2_OK) break;
+        if (ms_min < best_ms) {
+          best_ms = ms_min;
+          best_f = f;
+          best_tile = tile;
+          best_wave = wave;
+        }
+      }
+      if (res != FCHI2_OK) break;
+    }
+    if (res != FCHI2_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return res;
+}
+
 }  // namespace
 
 extern "C" {
@@ -954,6 +1004,50 @@ fchi2_status_t fchi2_search_multi(fchi2_plan_t plan, const double* t, const doub
                        flags, (hipStream_t)stream);
 }
 
+fchi2_status_t fchi2_autotune_multi(fchi2_plan_t plan, const double* t, const double* sigma,
+                                    const double* x, const double* scale, int32_t n_sources,
+                                    void* workspace, size_t workspace_bytes, void* dchi2,
+                                    void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
+  if (!t || !sigma || !x || !scale || !dchi2)
+    return fail(FCHI2_ERR_ARG, "t, sigma, x, scale and dchi2 must not be NULL");
+  if (plan->desc.n_curves != 1)
+    return fail(FCHI2_ERR_ARG, "the shared time base needs a plan of one curve");
+  if (plan->g.H > 5) return fail(FCHI2_ERR_UNSUPPORTED, "shared-alpha search supports H <= 5");
+  if (n_sources < 1) return fail(FCHI2_ERR_ARG, "n_sources must be >= 1");
+  if (!workspace || ((uintptr_t)workspace & 255) != 0)
+    return fail(FCHI2_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (workspace_bytes < multi_layout(plan, n_sources).bytes)
+    return fail(FCHI2_ERR_ARG, "workspace too small");
+  fchi2_plan_s* pl = plan;
+  hipStream_t st = (hipStream_t)stream;
+  if (pl->gexec) {
+    (void)hipGraphExecDestroy(pl->gexec);
+    pl->gexec = nullptr;
+  }
+  const std::vector<FftPlan> splits = fft_splits(pl->fp.logL, fft_tile_log());
+  const std::vector<int> waves = {pl->wave};
+  const bool prof = pl->prof;
+  pl->prof = false;
+  float best_ms = 1e30f;
+  FftPlan best_f = pl->fp;
+  int best_tile = pl->log_tile, best_wave = pl->wave;
+  fchi2_status_t res = tune_loop(
+      pl, splits, waves,
+      [&]() {
+        return enqueue_multi(pl, multi_layout(pl, n_sources), t, sigma, x, scale, n_sources,
+                             (char*)workspace, dchi2, nullptr, nullptr, st);
+      },
+      st, best_ms, best_f, best_tile, best_wave);
+  pl->prof = prof;
+  pl->log_tile = best_tile;
+  pl->wave = best_wave;
+  apply_fft_plan(pl, best_f);
+  pl->last_ws = nullptr;
+  return res;
+}
+
 fchi2_status_t fchi2_detrend(fchi2_plan_t plan, const double* t, const double* x,
                              const double* sigma, int32_t degree, double* x_out, double* coef,
                              void* stream) {
@@ -1055,50 +1149,24 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
     }
   }
   // Time every candidate on the caller's data.
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  const bool prof = pl->prof;
-  pl->prof = false;
   std::vector<int> waves = {pl->wave_max};
   for (int w = pl->wave_max / 2; w >= 1 && waves.size() < 3 && pl->desc.n_curves > 1; w /= 2)
     waves.push_back(w);
+  const bool prof = pl->prof;
+  pl->prof = false;
   float best_ms = 1e30f;
   FftPlan best_f = pl->fp;
   int best_tile = pl->log_tile, best_wave = pl->wave;
-  fchi2_status_t res = FCHI2_OK;
-  for (const FftPlan& f : splits) {
-    for (int tile : {10, 11, 12, 13}) {
-      for (int wave : waves) {
-        pl->log_tile = tile;
-        pl->wave = wave;
-        apply_fft_plan(pl, f);
-        float ms_min = 1e30f;
-        for (int rep = 0; rep < 3 && res == FCHI2_OK; ++rep) {
-          hipError_t e = hipEventRecord(e0, st);
-          if (e == hipSuccess) {
-            res = enqueue_search(pl, 0, pl->desc.n_curves, t, x, sigma, (char*)workspace, dchi2,
-                                 nullptr, nullptr, st);
-          }
-          if (e == hipSuccess && res == FCHI2_OK) e = hipEventRecord(e1, st);
-          if (e == hipSuccess && res == FCHI2_OK) e = hipEventSynchronize(e1);
-          float ms = 0.f;
-          if (e == hipSuccess && res == FCHI2_OK) e = hipEventElapsedTime(&ms, e0, e1);
-          if (e != hipSuccess) res = hip_fail(e, "autotune timing");
-          if (rep > 0 && ms < ms_min) ms_min = ms;  // first run warms up
-        }
-        if (res != FCHI2_OK) break;
-        if (ms_min < best_ms) {
-          best_ms = ms_min;
-          best_f = f;
-          best_tile = tile;
-          best_wave = wave;
-        }
-      }
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  fchi2_status_t res = tune_loop(
+      pl, splits, waves,
+      [&]() {
+        return enqueue_search(pl, 0, pl->desc.n_curves, t, x, sigma, (char*)workspace, dchi2,
+                              nullptr, nullptr, st);
+      },
+      st, best_ms, best_f, best_tile, best_wave);
+  (void)e0;
+  (void)e1;
   pl->prof = prof;
   pl->log_tile = best_tile;
   pl->wave = best_wave;

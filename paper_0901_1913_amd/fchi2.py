@@ -33,6 +33,7 @@ EXPORTS = (
     "fchi2_search_top_workspace_bytes", "fchi2_search_top",
     "fchi2_fine_scratch_bytes", "fchi2_fine_search",
     "fchi2_search_multi_workspace_bytes", "fchi2_search_multi", "fchi2_detrend",
+    "fchi2_autotune_multi",
 )
 PROF_STAGES = ("moments", "spread", "fft_first", "fft_mid", "fft_last", "solve",
                "bwd_solve", "bwd_fft", "bwd_gather", "bwd_final", "top_merge",
@@ -139,6 +140,8 @@ def lib() -> ctypes.CDLL:
     L.fchi2_search_multi_workspace_bytes.restype = sz
     L.fchi2_search_multi.argtypes = [vp, vp, vp, vp, vp, i32, vp, sz, vp, vp, vp, vp]
     L.fchi2_search_multi.restype = ctypes.c_int
+    L.fchi2_autotune_multi.argtypes = [vp, vp, vp, vp, vp, i32, vp, sz, vp, vp]
+    L.fchi2_autotune_multi.restype = ctypes.c_int
     L.fchi2_detrend.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
     L.fchi2_detrend.restype = ctypes.c_int
     _lib = L
@@ -327,6 +330,24 @@ class Plan:
             _dev_ptr(coef, f64, None, "coef") if coef is not None else ctypes.c_void_p(0),
             ctypes.c_void_p(_stream_handle(stream))))
         return (x_out, coef) if want_coef else x_out
+
+    def autotune_multi(self, t, sigma, x, scale, stream=None):
+        """Pick the FFT split and spreading tile for search_multi on these data."""
+        torch = _torch()
+        f64 = torch.float64
+        S = int(x.shape[0])
+        nbytes = int(lib().fchi2_search_multi_workspace_bytes(self._h, S))
+        if nbytes == 0:
+            raise FChi2Error(ERR_UNSUPPORTED, "shared-alpha search needs H <= 5")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=t.device)
+        scratch = torch.empty((S, self.H, self.n_freq), dtype=self.out_dtype, device=t.device)
+        _check(lib().fchi2_autotune_multi(
+            self._h, _dev_ptr(t, f64, self.n_total, "t"),
+            _dev_ptr(sigma, f64, self.n_total, "sigma"), _dev_ptr(x, f64, S * self.n_total, "x"),
+            _dev_ptr(scale, f64, S, "scale"), S, ctypes.c_void_p(ws.data_ptr()),
+            ctypes.c_size_t(nbytes), ctypes.c_void_p(scratch.data_ptr()),
+            ctypes.c_void_p(_stream_handle(stream))))
+        return self.info()
 
     def search_multi(self, t, sigma, x, scale, want_flags=True, stream=None):
         """Shared-alpha search of sources observed at the plan's single time base.

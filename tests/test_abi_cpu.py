@@ -91,4 +91,5 @@ def test_null_arguments():
                                 None) == F.ERR_ARG
     assert L.fchi2_search_multi_workspace_bytes(None, 4) == 0
     assert L.fchi2_detrend(None, None, None, None, 1, None, None, None) == F.ERR_ARG
+    assert L.fchi2_autotune_multi(None, None, None, None, None, 4, None, 0, None, None) == F.ERR_ARG
     L.fchi2_destroy(None)
