@@ -245,6 +245,58 @@ def multi_vs_curves(steps):
             "unit": "freq*H/s"}
 
 
+def gradient_timing(steps):
+    """Adjoint of the search on the diff workload: forward with the spectra
+    kept, top-16 strict local maxima of the H row frozen, then the gradient
+    of the sum of their Delta chi2 with respect to x and sigma."""
+    import torch
+    from paper_0901_1913_amd import fchi2 as F
+    from paper_0901_1913_amd import synth
+    cur = synth.make("diff")
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision,
+                  keep_for_backward=True)
+    t = torch.from_numpy(cur.t).cuda()
+    x = torch.from_numpy(cur.x).cuda()
+    s = torch.from_numpy(cur.sigma).cuda()
+    schedule = plan.autotune(t, x, s)
+    d, _, _ = plan.search(t, x, s)
+    span = float(cur.t[-1] - cur.t[0])
+    df = cur.f_max / cur.n_freq
+    idx = plan.top_peaks(d, cur.H - 1, int(np.ceil(1.0 / (span * df))), 16)
+    g = torch.zeros_like(d)
+    g[0, cur.H - 1, idx[0]] = 1.0
+    plan.backward(t, x, s, g)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.search(t, x, s, dchi2=d)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_f = e0.elapsed_time(e1) / steps
+    plan.profile(True)
+    e0.record(stream)
+    for _ in range(steps):
+        gx, gs = plan.backward(t, x, s, g)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / steps
+    st = plan.profile_read()
+    plan.profile(False)
+    plan.close()
+    units = cur.n_freq * cur.H
+    log(f"gradient (diff): forward {ms_f:.4f} ms, backward {ms_b:.4f} ms")
+    return {"workload": "diff", "n": int(cur.t.shape[0]), "H": cur.H, "n_freq": cur.n_freq,
+            "precision": cur.precision, "forward_ms": round(ms_f, 5),
+            "backward_ms": round(ms_b, 5),
+            "backward_value": round(units / (ms_b * 1e-3), 1), "unit": "freq*H/s",
+            "backward_stages_ms": {k: round(v[0] / steps, 5) for k, v in st.items()
+                                   if v[1] and k.startswith("bwd")},
+            "schedule": schedule}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +311,8 @@ def main(argv=None):
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-multi", action="store_true",
                     help="skip the shared-alpha multi-source comparison")
+    ap.add_argument("--no-gradient", action="store_true",
+                    help="skip the adjoint timing on the diff workload")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device copy of this many MiB (a known-size kernel "
                          "against which HBM counters are scaled)")
@@ -419,6 +473,8 @@ def main(argv=None):
         out["batched"] = batched_vs_plain(a.batched_steps)
     if not a.no_multi:
         out["multi"] = multi_vs_curves(a.batched_steps)
+    if not a.no_gradient:
+        out["gradient"] = gradient_timing(a.steps)
     print(json.dumps(out), flush=True)
     return 0
 
