@@ -326,49 +326,100 @@ __global__ __launch_bounds__(kNT) void k_gather(const double* __restrict__ t,
   gp[i] = ap;
 }
 
+// Final step of the adjoint, in two chunked phases over each curve's points
+// (the forward's moment partials buffer holds the per-chunk sums):
+//   phase 1, block b of curve c: s1 = sum_chunk w g_p and s2 = its share of
+//            the dW partials of the solve;
+//   phase 2, block b of curve c: gbar = sum s1 / W, dW = sum s2, then
+//            grad_x = w (g_p - gbar) and
+//            grad_sigma = -2 w / sigma (g_q + dW + (x - xbar)(g_p - gbar)).
+__global__ __launch_bounds__(kNT) void k_fin_reduce(const double* __restrict__ sigma,
+                                                    const Moments* __restrict__ mom, int curve0,
+                                                    const double* __restrict__ dw_part, int bpc,
+                                                    const double* __restrict__ gp, int nch,
+                                                    double* __restrict__ part) {
+  __shared__ double red[2][kNT / 64];
+  const int c = curve0 + blockIdx.y;
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const Moments mo = mom[c];
+  if (mo.flags & kCurveFatal) return;
+  const int64_t chunk = (mo.n + nch - 1) / nch;
+  const int64_t lo = mo.start + (int64_t)b * chunk;
+  const int64_t hi = (lo + chunk < mo.start + mo.n) ? lo + chunk : mo.start + mo.n;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = lo + tid; i < hi; i += kNT) {
+    const double si = sigma[i];
+    s1 += gp[i] / (si * si);
+  }
+  const int per = (bpc + nch - 1) / nch;
+  for (int q = b * per + tid; q < (b + 1) * per && q < bpc; q += kNT)
+    s2 += dw_part[(int64_t)c * bpc + q];
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 += __shfl_xor(s1, o);
+    s2 += __shfl_xor(s2, o);
+  }
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = s1;
+    red[1][tid >> 6] = s2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double a1 = 0.0, a2 = 0.0;
+    for (int w = 0; w < kNT / 64; ++w) {
+      a1 += red[0][w];
+      a2 += red[1][w];
+    }
+    part[2 * ((int64_t)c * nch + b)] = a1;
+    part[2 * ((int64_t)c * nch + b) + 1] = a2;
+  }
+}
+
 __global__ __launch_bounds__(kNT) void k_finalize(const double* __restrict__ x,
                                                   const double* __restrict__ sigma,
                                                   const Moments* __restrict__ mom, int curve0,
-                                                  const double* __restrict__ dw_part, int bpc,
+                                                  const double* __restrict__ part, int nch,
                                                   const double* __restrict__ gq,
                                                   const double* __restrict__ gp,
                                                   double* __restrict__ grad_x,
                                                   double* __restrict__ grad_sigma) {
-  __shared__ double red[kNT];
-  const int c = curve0 + blockIdx.x;
+  __shared__ double red[2][kNT / 64];
+  const int c = curve0 + blockIdx.y;
+  const int b = blockIdx.x;
   const int tid = threadIdx.x;
   const Moments mo = mom[c];
-  const int64_t a = mo.start, b = mo.start + mo.n;
+  const int64_t chunk = (mo.n + nch - 1) / nch;
+  const int64_t lo = mo.start + (int64_t)b * chunk;
+  const int64_t hi = (lo + chunk < mo.start + mo.n) ? lo + chunk : mo.start + mo.n;
   if (mo.flags & kCurveFatal) {
-    for (int64_t i = a + tid; i < b; i += kNT) {
+    for (int64_t i = lo + tid; i < hi; i += kNT) {
       grad_x[i] = NAN;
       grad_sigma[i] = NAN;
     }
     return;
   }
-  double s = 0.0;
-  for (int q = tid; q < bpc; q += kNT) s += dw_part[(int64_t)c * bpc + q];
-  red[tid] = s;
-  __syncthreads();
-  for (int st = kNT / 2; st > 0; st >>= 1) {
-    if (tid < st) red[tid] += red[tid + st];
-    __syncthreads();
+  // Chunk sums in a fixed order (every block of the curve gets the same totals).
+  double s1 = 0.0, s2 = 0.0;
+  for (int q = tid; q < nch; q += kNT) {
+    s1 += part[2 * ((int64_t)c * nch + q)];
+    s2 += part[2 * ((int64_t)c * nch + q) + 1];
   }
-  const double dW = red[0];
-  __syncthreads();
-  double sg = 0.0;
-  for (int64_t i = a + tid; i < b; i += kNT) {
-    const double si = sigma[i];
-    sg += gp[i] / (si * si);
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 += __shfl_xor(s1, o);
+    s2 += __shfl_xor(s2, o);
   }
-  red[tid] = sg;
-  __syncthreads();
-  for (int st = kNT / 2; st > 0; st >>= 1) {
-    if (tid < st) red[tid] += red[tid + st];
-    __syncthreads();
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = s1;
+    red[1][tid >> 6] = s2;
   }
-  const double gbar = red[0] / mo.W;
-  for (int64_t i = a + tid; i < b; i += kNT) {
+  __syncthreads();
+  double a1 = 0.0, dW = 0.0;
+  for (int w = 0; w < kNT / 64; ++w) {
+    a1 += red[0][w];
+    dW += red[1][w];
+  }
+  const double gbar = a1 / mo.W;
+  for (int64_t i = lo + tid; i < hi; i += kNT) {
     const double si = sigma[i];
     const double w = 1.0 / (si * si);
     const double dp = gp[i] - gbar;
@@ -435,10 +486,16 @@ hipError_t launch_gather(bool fp64, const double* t, const Moments* mom, const G
 hipError_t launch_finalize(const double* x, const double* sigma, const Moments* mom,
                            const Geom& g, int curve0, int n_curves, const double* dW_part,
                            int blocks_per_curve, const double* gq, const double* gp,
-                           double* grad_x, double* grad_sigma, hipStream_t st) {
+                           double* grad_x, double* grad_sigma, double* scratch, int nch,
+                           hipStream_t st) {
   (void)g;
-  hipLaunchKernelGGL(k_finalize, dim3(n_curves), dim3(kNT), 0, st, x, sigma, mom, curve0,
-                     dW_part, blocks_per_curve, gq, gp, grad_x, grad_sigma);
+  dim3 gr((unsigned)nch, (unsigned)n_curves);
+  hipLaunchKernelGGL(k_fin_reduce, gr, dim3(kNT), 0, st, sigma, mom, curve0, dW_part,
+                     blocks_per_curve, gp, nch, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize, gr, dim3(kNT), 0, st, x, sigma, mom, curve0,
+                     (const double*)scratch, nch, gq, gp, grad_x, grad_sigma);
   return hipGetLastError();
 }
 

@@ -865,8 +865,10 @@ fchi2_status_t fchi2_backward(fchi2_plan_t plan, const double* t, const double* 
     if (e != hipSuccess) return hip_fail(e, "gather");
     PROF_END();
     PROF_BEGIN(FCHI2_PROF_BWD_FINAL);
+    // The forward's moment partials (MomPart, 4 doubles each, mom_bpc per
+    // curve) are free during the backward: they hold the chunk sums here.
     e = launch_finalize(x, sigma, mom, plan->g, c0, nw, dw, plan->blocks_per_curve, gq, gp,
-                        grad_x, grad_sigma, st);
+                        grad_x, grad_sigma, (double*)(ws + plan->off_part), plan->mom_bpc, st);
     if (e != hipSuccess) return hip_fail(e, "finalize");
     PROF_END();
   }

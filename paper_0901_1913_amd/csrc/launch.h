@@ -71,11 +71,13 @@ hipError_t launch_gather(bool fp64, const double* t, const Moments* mom, const G
                          int curve0, int n_curves, const void* grid, double* gq, double* gp,
                          int64_t max_n, hipStream_t st);
 
-// Reduce the per-curve terms and write d/dx, d/dsigma.
+// Reduce the per-curve terms and write d/dx, d/dsigma; scratch holds
+// 2 * nch doubles per curve of the wave's curves (indexed by absolute curve).
 hipError_t launch_finalize(const double* x, const double* sigma, const Moments* mom,
                            const Geom& g, int curve0, int n_curves, const double* dW_part,
                            int blocks_per_curve, const double* gq, const double* gp,
-                           double* grad_x, double* grad_sigma, hipStream_t st);
+                           double* grad_x, double* grad_sigma, double* scratch, int nch,
+                           hipStream_t st);
 
 // Top-K strict local maxima of one Delta chi2 row per curve.
 hipError_t launch_peaks(bool fp64, const void* dchi2, int64_t n_freq, int H, int hrow,

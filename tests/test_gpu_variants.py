@@ -33,14 +33,17 @@ def test_floor_gridding_matches_quantized_oracle(precision, tol):
     gate = ora.gate_mask(r, fr, 1e2 if precision == "mixed" else 1e6)
     e = ora.rel_err(d[0][:, bins], r["dchi2"])[:, gate]
     ex = ora.dchi2(cur.t, cur.x, cur.sigma, fr, cur.H)["dchi2"]
+    # The paper's sensitivity loss: the cell jitter dt = 1 / (L df) costs little
+    # at the signal (f0 dt << 1) and a lot near f_max (harmonic phases jitter by
+    # up to 2 pi H f dt).
+    dev = ora.rel_err(r["dchi2"], ex)[-1]
     hi = bins >= cur.n_freq // 2
-    loss = np.median((ex[-1] - r["dchi2"][-1])[hi] / np.maximum(ex[-1][hi], 1.0))
+    sig = bins == k0
     print(f"floor {precision}: max gated rel err vs quantized oracle {e.max():.3e}; "
-          f"exact vs floor-gridded at the signal {ex[-1][bins == k0][0]:.2f} vs "
-          f"{r['dchi2'][-1][bins == k0][0]:.2f}", flush=True)
+          f"vs the exact search: {dev[sig][0]:.2e} at the signal, median {np.median(dev[hi]):.2e} "
+          f"above f_max/2", flush=True)
     assert e.max() <= tol
-    assert (fl[0][bins] & F.BIN_PIVOT).sum() == 0 or True
-    del loss
+    assert dev[sig][0] < 1e-2 and np.median(dev[hi]) > 1e-2
 
 
 def test_floor_gridding_rejects_backward():
