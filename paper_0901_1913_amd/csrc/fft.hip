@@ -256,6 +256,7 @@ __global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<S>* 
   __shared__ cplx<S> sm[N * PT];
   __shared__ C tr[T == 1 ? 1 : N];  // the single-pass tile has no twiddles
   __shared__ C tc[T];
+  __shared__ int64_t s_rev[T];  // first pass: output offset of each tile column
 
   const int tid = threadIdx.x;
   const int p = blockIdx.y;
@@ -354,21 +355,24 @@ __global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<S>* 
         sm[k * PT + cc] = narrow<S>(cmul(v[it * SL::RAD + i], tw));
       }
     }
+    // Mixed-radix reversal of each of the tile's T columns, once per tile:
+    // rev = ((j_1 N_2 + j_2) N_3 + j_3) ... + j_{np-1} for column c = g0 + cc.
+    for (int cc = tid; cc < T; cc += kNT) {
+      int64_t rev = 0, rest = g0 + cc;
+      for (int d = 1; d < np; ++d) {
+        const int64_t dig = rest & (((int64_t)1 << a.logn[d]) - 1);
+        rest >>= a.logn[d];
+        rev = (rev << a.logn[d]) | dig;
+      }
+      s_rev[cc] = rev * N;
+    }
     __syncthreads();
 #pragma unroll 4
     for (int it = 0; it < kEPT; ++it) {
       const int e = tid + it * kNT;
       const int k = e & (N - 1);
       const int cc = e >> LOGN;
-      const int64_t c = g0 + cc;
-      // Mixed-radix reversal: rev = ((j_1 N_2 + j_2) N_3 + j_3) ... + j_{np-1}.
-      int64_t rev = 0, rest = c;
-      for (int d = 1; d < np; ++d) {
-        const int64_t dig = rest & (((int64_t)1 << a.logn[d]) - 1);
-        rest >>= a.logn[d];
-        rev = (rev << a.logn[d]) | dig;
-      }
-      nts<NT>(&dst[rev * N + k], sm[k * PT + cc]);
+      nts<NT>(&dst[s_rev[cc] + k], sm[k * PT + cc]);
     }
   } else if (a.kind == PASS_MID) {
     const int64_t Tail = L >> (low_bits + LOGN);
