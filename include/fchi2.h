@@ -26,8 +26,11 @@
  *    device work is enqueued on it; no call synchronises the stream, except
  *    fchi2_plan, which initialises plan tables and returns after they are
  *    ready.
- *  - fchi2_search, fchi2_backward and fchi2_top_peaks allocate no memory and
- *    make no blocking call, so they may be captured in a HIP graph.
+ *  - fchi2_search(_curves), fchi2_backward, fchi2_top_peaks,
+ *    fchi2_search_top, fchi2_fine_search, fchi2_search_multi and
+ *    fchi2_detrend allocate no memory and make no blocking call, so they may
+ *    be captured in a HIP graph (fchi2_autotune and fchi2_autotune_multi
+ *    synchronise).
  *  - Errors are reported by the return code only (no exceptions, no abort);
  *    fchi2_last_error() gives a message for the calling thread.  Argument
  *    errors are detected on the host before any device work is enqueued.
@@ -60,8 +63,8 @@ typedef enum {
 
 typedef enum {
   FCHI2_FP64 = 0,   /* FP64 spreading, FFT, assembly and solve                */
-  FCHI2_MIXED = 1   /* FP64 phase reduction, moments and solve; FP32 grids,
-                       FFT and spectra; FP32 Delta chi2 output               */
+  FCHI2_MIXED = 1   /* FP64 arithmetic throughout; grids, spectra and the
+                       Delta chi2 output stored in FP32 (FP32 HBM traffic)   */
 } fchi2_precision_t;
 
 /* Plan flags. */

@@ -329,7 +329,8 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
       }
       __syncthreads();
       // First point with j0 >= c - hw - 1, found by binary search for every
-      // fourth cell (one search per thread); cells in between advance from it.
+      // (B / 256)-th cell (one search per thread); cells in between advance
+      // from it.
       {
         const int cs = tid * (B / kNT);
         int lo = 0, hi = cnt;
