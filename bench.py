@@ -42,7 +42,7 @@ def measured_traffic(workload):
         return {}
     meta = json.loads(m.group(1))
     src = {"fft_first": ["fft.hip"], "fft_mid": ["fft.hip"], "fft_last": ["fft.hip"],
-           "solve": ["solve.hip", "solve_bin.h"], "spread": ["spread.hip"]}
+           "solve": ["solve.hip", "solve_bin.h"], "spread": ["spread.hip", "es_kernel.h"]}
     out = {}
     for st, nbytes in meta.get("bytes_per_launch", {}).items():
         h = hashlib.sha256()

@@ -21,6 +21,7 @@
 
 #include "fchi2_internal.h"
 #include "launch.h"
+#include "es_kernel.h"
 
 namespace fchi2 {
 
@@ -267,22 +268,6 @@ __global__ __launch_bounds__(kNT) void k_adjoint(const cplx<R>* __restrict__ zc,
     __syncthreads();
   }
   if (tid == 0) dw_part[(int64_t)c * bpc + blockIdx.x] = red[0];
-}
-
-// Same kernel evaluation as the spreading (FP64 argument; FP32 exponential
-// with its rounding residual corrected unless EXACT).
-template <bool EXACT>
-__device__ __forceinline__ double es_kernel(double z, double beta) {
-  const double q = 1.0 - z * z;
-  if (!(q > 0.0)) return 0.0;
-  const double arg = beta * (sqrt(q) - 1.0);
-  if constexpr (EXACT) {
-    return exp(arg);
-  } else {
-    const float a = (float)arg;
-    const double r = arg - (double)a;
-    return (double)expf(a) * (1.0 + r);
-  }
 }
 
 template <typename S>

@@ -24,6 +24,7 @@
 
 #include "fchi2_internal.h"
 #include "launch.h"
+#include "es_kernel.h"
 
 namespace fchi2 {
 
@@ -164,12 +165,17 @@ __global__ __launch_bounds__(kNT) void k_moments_fin(const double* __restrict__ 
 // Floor gridding (kernel width 1, Section 3b): the point's time is replaced by
 // the start of its cell, floor(v L), and harmonic m sits at m times that cell
 // (an exact integer); the kernel weight is then 1 at that cell only.
+__device__ __forceinline__ double cell_at(double ti, double T0, double df, int m, double L,
+                                          double c_off, bool flr) {
+  const double v = (ti - T0) * df;
+  if (flr) return (double)m * floor(v * L);
+  return ((double)m * v) * L + c_off;
+}
+
 __device__ __forceinline__ double cell_pos(const double* __restrict__ t, int64_t i, double T0,
                                            double df, int m, double L, double c_off,
                                            bool flr) {
-  const double v = (t[i] - T0) * df;
-  if (flr) return (double)m * floor(v * L);
-  return ((double)m * v) * L + c_off;
+  return cell_at(t[i], T0, df, m, L, c_off, flr);
 }
 
 // Tile -> point-range table.  For harmonic m and tile t of B cells, the
@@ -181,11 +187,15 @@ __device__ __forceinline__ double cell_pos(const double* __restrict__ t, int64_t
 // Entries stop at tile_limit(): tiles past it hold no point of harmonic m.
 // Last table entry written for harmonic m: the tile after the one holding the
 // last point's footprint, plus the two-tile lookahead of the spreading.
+__device__ __forceinline__ int64_t tile_limit_of(double t_last, const Moments& mo,
+                                                 const Geom& g, int m, int log_tile) {
+  const double last = cell_at(t_last, mo.T0, g.df, m, (double)g.L, (double)g.c_off, g.w == 1);
+  return (int64_t)floor((last + (double)(g.w / 2 + 2)) / (double)((int64_t)1 << log_tile)) + 3;
+}
+
 __device__ __forceinline__ int64_t tile_limit(const double* __restrict__ t, const Moments& mo,
                                               const Geom& g, int m, int log_tile) {
-  const double last = cell_pos(t, mo.start + mo.n - 1, mo.T0, g.df, m, (double)g.L,
-                               (double)g.c_off, g.w == 1);
-  return (int64_t)floor((last + (double)(g.w / 2 + 2)) / (double)((int64_t)1 << log_tile)) + 3;
+  return tile_limit_of(t[mo.start + mo.n - 1], mo, g, m, log_tile);
 }
 
 __global__ __launch_bounds__(kNT) void k_tile_bounds(const double* __restrict__ t,
@@ -220,25 +230,6 @@ __global__ __launch_bounds__(kNT) void k_tile_bounds(const double* __restrict__ 
   for (int64_t q = t_min; q <= t_max; ++q) row[q] = (int32_t)il;
 }
 
-// Exponential-of-semicircle kernel exp(beta (sqrt(1 - z^2) - 1)) on |z| < 1.
-// The argument is formed in FP64.  With EXACT the exponential is FP64 too;
-// otherwise the FP32 exponential of the rounded argument is corrected by the
-// rounding residual, exp(a + r) = exp(a) (1 + r + O(r^2)), which keeps the
-// kernel value within about one FP32 ulp although the argument reaches -2.3 w.
-template <bool EXACT>
-__device__ __forceinline__ double es_kernel(double z, double beta) {
-  const double q = 1.0 - z * z;
-  if (!(q > 0.0)) return 0.0;
-  const double arg = beta * (sqrt(q) - 1.0);
-  if constexpr (EXACT) {
-    return exp(arg);
-  } else {
-    const float a = (float)arg;
-    const double r = arg - (double)a;
-    return (double)expf(a) * (1.0 + r);
-  }
-}
-
 template <typename S, int LOGB>
 __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
                                                 const double* __restrict__ x,
@@ -251,10 +242,8 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
   constexpr int B = 1 << LOGB;
   constexpr int CPT = B / kNT;
   constexpr int CH = 1024;
-  __shared__ int s_j0[CH];
-  __shared__ double s_fr[CH];
-  __shared__ double s_re[CH];
-  __shared__ double s_im[CH];
+  __shared__ double s_p[CH];  // cell coordinate relative to the tile start (exact)
+  __shared__ double2 s_v[CH];  // strengths of the real and imaginary parts
   __shared__ int s_first[kNT];
 
   const int tid = threadIdx.x;
@@ -265,6 +254,7 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
   // (cells beyond the extent are never read); blocks stride over them.
   int64_t items = 0;
   for (int q = 0; q < g.P; ++q) items += pair_extent(mo, g, q) >> LOGB;
+  const double t_last = t[mo.start + mo.n - 1];
   for (int64_t wi = blockIdx.x; wi < items; wi += gridDim.x) {
   int p = 0;
   int64_t tile = wi;
@@ -278,6 +268,7 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
 
   const int hw = g.w / 2;
   const double two_over_w = 2.0 / (double)g.w;
+  const double hreach = (double)(hw + 1);
   const double beta = g.beta;
   const double Ld = (double)g.L;
   const double coff = (double)g.c_off;
@@ -290,26 +281,35 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
     acc_im[u] = 0.0;
   }
 
+  // Point ranges of both components, loaded together before either is staged.
+  int64_t rng_lo[2] = {0, 0}, rng_hi[2] = {0, 0};
+#pragma unroll
   for (int comp = 0; comp < 2; ++comp) {
     const int m = g.comp_m[p][comp];
     if (m == 0) continue;
     if (comp == 1 && m == g.comp_m[p][0]) continue;  // shared with component 0
+    // No point of harmonic m reaches tiles past tile_limit - 2.
+    if (tile + 2 > tile_limit_of(t_last, mo, g, m, LOGB)) continue;
+    const int32_t* row = tb + ((int64_t)(share_tb ? 0 : cw) * (2 * g.H) + (m - 1)) * ntb;
+    rng_lo[comp] = pa + row[tile];
+    rng_hi[comp] = pa + row[tile + 2];
+  }
+
+  for (int comp = 0; comp < 2; ++comp) {
+    const int m = g.comp_m[p][comp];
+    const int64_t i_lo = rng_lo[comp], i_hi = rng_hi[comp];
+    if (i_hi <= i_lo) continue;  // no points (or component absent / shared)
     const bool both = (comp == 0) && (g.comp_m[p][1] == m);
     const int kind_a = g.comp_kind[p][comp];
     const int kind_b = both ? g.comp_kind[p][1] : -1;
-    // No point of harmonic m reaches tiles past tile_limit - 2.
-    if (tile + 2 > tile_limit(t, mo, g, m, LOGB)) continue;
-    const int32_t* row = tb + ((int64_t)(share_tb ? 0 : cw) * (2 * g.H) + (m - 1)) * ntb;
-    const int64_t i_lo = pa + row[tile], i_hi = pa + row[tile + 2];
 
     for (int64_t ch = i_lo; ch < i_hi; ch += CH) {
       const int cnt = (int)((i_hi - ch) < CH ? (i_hi - ch) : CH);
       for (int q = tid; q < cnt; q += kNT) {
         const int64_t i = ch + q;
-        // floor gridding: pos is an integer, fr = 0 and the kernel below is
+        // floor gridding: pos is an integer and the kernel below is
         // exp(0) = 1 at d = 0 and 0 at |d| >= 1 (w = 1)
         const double pos = cell_pos(t, i, mo.T0, g.df, m, Ld, coff, g.w == 1);
-        const double fl = floor(pos);
         const double si = sigma[i];
         const double w = 1.0 / (si * si);
         const double wy = w * (x[i + mo.xshift] - mo.xbar);
@@ -322,22 +322,23 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
           sre = 0.0;
           sim = sa;
         }
-        s_j0[q] = (int)((int64_t)fl - a0);
-        s_fr[q] = pos - fl;
-        s_re[q] = sre;
-        s_im[q] = sim;
+        // pos - a0 is exact (a multiple of pos's ulp, smaller than pos), and
+        // so is jl - s_p below: the same kernel argument as jl - cell - frac.
+        s_p[q] = pos - (double)a0;
+        s_v[q] = make_double2(sre, sim);
       }
       __syncthreads();
-      // First point with j0 >= c - hw - 1, found by binary search for every
-      // (B / 256)-th cell (one search per thread); cells in between advance
-      // from it.
+      // Cell jl takes the points with floor(p) in [jl - hw - 1, jl + hw], i.e.
+      // jl - hw - 1 <= p < jl + hw + 1.  The first of them is found by binary
+      // search for every (B / 256)-th cell (one search per thread); cells in
+      // between advance from it.
       {
         const int cs = tid * (B / kNT);
         int lo = 0, hi = cnt;
-        const int key = cs - hw - 1;
+        const double key = (double)(cs - hw - 1);
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (s_j0[mid] < key) lo = mid + 1;
+          if (s_p[mid] < key) lo = mid + 1;
           else hi = mid;
         }
         s_first[tid] = lo;
@@ -346,16 +347,18 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
 #pragma unroll
       for (int u = 0; u < CPT; ++u) {
         const int jl = tid + u * kNT;
+        // with d = jl - p the window is -(hw + 1) < d <= hw + 1
+        const double cl = (double)jl;
         int q = s_first[jl / (B / kNT)];
-        while (q < cnt && s_j0[q] < jl - hw - 1) ++q;
+        while (q < cnt && cl - s_p[q] > hreach) ++q;
         double ar = acc_re[u], ai = acc_im[u];
         for (int r = q; r < cnt; ++r) {
-          const int j0 = s_j0[r];
-          if (j0 > jl + hw) break;
-          const double d = (double)(jl - j0) - s_fr[r];
+          const double d = cl - s_p[r];
+          if (d <= -hreach) break;
           const double phi = es_kernel<EXACT>(d * two_over_w, beta);
-          ar += phi * s_re[r];
-          ai += phi * s_im[r];
+          const double2 v = s_v[r];
+          ar += phi * v.x;
+          ai += phi * v.y;
         }
         acc_re[u] = ar;
         acc_im[u] = ai;
