@@ -367,7 +367,9 @@ fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* 
  * (the FFT digit splits with the fewest passes and the most balanced splits
  * with one pass more, spreading tiles of 1024 to
  * 8192 cells, and waves of wave_max, wave_max/2, wave_max/4 curves) with HIP
- * events on `stream`, keeps the fastest in the plan, and appends it to the
+ * events on `stream` (two timed runs each after a warm-up, then the three
+ * fastest five more times each, in turns), keeps the fastest in the plan,
+ * and appends it to the
  * text file `cache_path` (may be NULL) keyed by the shape bucket (H, n_freq,
  * precision, kernel width, log2 curves, log2 largest curve, wave_max).  If
  * the file already holds the key, the cached schedule is applied without
