@@ -63,8 +63,9 @@ typedef enum {
 
 typedef enum {
   FCHI2_FP64 = 0,   /* FP64 spreading, FFT, assembly and solve                */
-  FCHI2_MIXED = 1   /* FP64 arithmetic throughout; grids, spectra and the
-                       Delta chi2 output stored in FP32 (FP32 HBM traffic)   */
+  FCHI2_MIXED = 1   /* FP64 arithmetic (the spreading kernel's exponential to
+                       FP32 accuracy); grids, spectra and the Delta chi2
+                       output stored in FP32 (FP32 HBM traffic)              */
 } fchi2_precision_t;
 
 /* Plan flags. */
