@@ -36,6 +36,7 @@
 #include "fchi2_internal.h"
 #include "launch.h"
 #include "solve_bin.h"
+#include "wave_min.h"
 
 namespace fchi2 {
 
@@ -75,8 +76,8 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
   __shared__ O s_d[H][kSpan];
   __shared__ uint8_t s_fl[kSpan];
   __shared__ double s_red[kNT / 64];
-  __shared__ double t_s[2][kNT / 64];
-  __shared__ int t_i[2][kNT / 64];
+  __shared__ double w_s[kNT / 64][64];  // each wave's K best keys, in order
+  __shared__ int w_i[kNT / 64][64];
   __shared__ int s_win[64];
 
   const int tid = threadIdx.x;
@@ -147,13 +148,16 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
       }
     }
   }
-  // Tournament: K rounds of block arg-min over the threads' heads.  The two
-  // LDS buffers alternate, so one barrier per round suffices.
+  // Tournament inside each wave: K rounds of wave arg-min over the threads'
+  // heads (DPP permutations, no barrier); lane r keeps the r-th winner and
+  // the winner's owner advances.  Every key of a wave is held by that wave.
+  const int lane = tid & 63, wv = tid >> 6;
   int head = 0;
-  int rounds = 0;
+  double my_s = INFINITY;
+  int my_i = INT_MAX;
   for (int r = 0; r < K; ++r) {
     double sv = INFINITY;
-    int si = 0x7fffffff;
+    int si = INT_MAX;
 #pragma unroll
     for (int q = 0; q < kBPT; ++q) {
       if (q == head) {
@@ -161,35 +165,47 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
         si = ki[q];
       }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double os = __shfl_xor(sv, o);
-      const int oi = __shfl_xor(si, o);
-      if (key_less(os, oi, sv, si)) {
-        sv = os;
-        si = oi;
-      }
+    wave_min_key(sv, si);
+    if (!(sv < INFINITY)) break;  // the same decision in every lane of the wave
+    if (lane == r) {
+      my_s = sv;
+      my_i = si;
     }
-    const int buf = r & 1;
-    if ((tid & 63) == 0) {
-      t_s[buf][tid >> 6] = sv;
-      t_i[buf][tid >> 6] = si;
-    }
-    __syncthreads();
-    double bs = t_s[buf][0];
-    int bi = t_i[buf][0];
-#pragma unroll
-    for (int w = 1; w < kNT / 64; ++w) {
-      if (key_less(t_s[buf][w], t_i[buf][w], bs, bi)) {
-        bs = t_s[buf][w];
-        bi = t_i[buf][w];
-      }
-    }
-    if (!(bs < INFINITY)) break;  // the same decision in every thread
-    if (tid == 0) s_win[r] = bi;
-    if ((bi & (kNT - 1)) == tid) ++head;
-    rounds = r + 1;
+    if ((si & (kNT - 1)) == tid) ++head;
+  }
+  if (lane < K) {
+    w_s[wv][lane] = my_s;
+    w_i[wv][lane] = my_i;
   }
   __syncthreads();
+  // Merge of the sorted wave lists: a finite key's rank is its position in its
+  // list plus the number of smaller keys in the other lists (keys are
+  // distinct, so ranks are); the K first ranks are the block's K best.
+  bool wrote = false;
+  if (tid < (kNT / 64) * K) {
+    const int L = tid / K, pos = tid - L * K;
+    const double sv = w_s[L][pos];
+    const int si = w_i[L][pos];
+    if (sv < INFINITY) {
+      int rank = pos;
+#pragma unroll
+      for (int L2 = 0; L2 < kNT / 64; ++L2) {
+        if (L2 == L) continue;
+        int a = 0, b = K;  // first index of list L2 whose key is not smaller
+        while (a < b) {
+          const int mid = (a + b) >> 1;
+          if (key_less(w_s[L2][mid], w_i[L2][mid], sv, si)) a = mid + 1;
+          else b = mid;
+        }
+        rank += a;
+      }
+      if (rank < K) {
+        s_win[rank] = si;
+        wrote = true;
+      }
+    }
+  }
+  const int rounds = __syncthreads_count(wrote);
 
   const int64_t base = ((int64_t)cw * nblk + blockIdx.x) * K;
   if (tid < K) {
@@ -211,25 +227,29 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
 
 // One merge step: group g of curve slot cw takes up to 256 sorted lists (one
 // per thread; list l = g * 256 + tid of the nl lists of the curve) and keeps
-// their K smallest keys (ln p, k), in order, by the tournament of the solve
-// kernel.  Records are referred to by their index q in the phase-1 arrays
-// (in_q null: the input is phase 1 itself).  With `fin` set (one group per
-// curve) it writes the user outputs instead of a list.
+// their K smallest keys (ln p, k), in order: a tournament inside each wave as
+// in the solve kernel (each thread holds its list's next four records in
+// registers), then the rank merge of the four wave lists.  Records are
+// referred to by their index q in the phase-1 arrays (in_q null: the input is
+// phase 1 itself).  With `fin` set (one group per curve) it writes the user
+// outputs instead of a list.
 __global__ __launch_bounds__(kNT) void k_top_merge(
     const double* __restrict__ in_s, const int64_t* __restrict__ in_k,
     const int64_t* __restrict__ in_q, const double* __restrict__ in_max, int nl, int K,
     double* __restrict__ o_s, int64_t* __restrict__ o_k, int64_t* __restrict__ o_q,
     double* __restrict__ o_max, int fin, const Moments* __restrict__ mom, int curve0, int H,
     int hrow, const uint8_t* __restrict__ rf, const double* __restrict__ rd, TopOut out) {
-  __shared__ double t_s[2][kNT / 64];
-  __shared__ int64_t t_k[2][kNT / 64];
-  __shared__ int t_l[2][kNT / 64];
-  __shared__ double s_ws[64];   // winning score per round
-  __shared__ int64_t s_wk[64];  // winning bin per round
-  __shared__ int64_t s_wq[64];  // winning phase-1 record per round
+  constexpr int PF = 4;  // records of a list held in registers at a time
+  __shared__ double w_s[kNT / 64][64];  // each wave's K best, in order
+  __shared__ int w_k[kNT / 64][64];
+  __shared__ int64_t w_q[kNT / 64][64];
+  __shared__ double s_ws[64];   // the group's K best: score,
+  __shared__ int64_t s_wk[64];  // bin,
+  __shared__ int64_t s_wq[64];  // phase-1 record
   __shared__ double s_mx[kNT / 64];
 
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const int g = blockIdx.x;
   const int cw = blockIdx.y;
   const int ng = gridDim.x;
@@ -244,60 +264,91 @@ __global__ __launch_bounds__(kNT) void k_top_merge(
   }
   if ((tid & 63) == 0) s_mx[tid >> 6] = mx;
 
-  int head = 0;
-  int rounds = 0;
-  for (int r = 0; r < K; ++r) {
-    double sv = INFINITY;
-    int64_t sk = INT64_MAX;
-    int sl = -1;
-    if (l < nl && head < K) {
-      const int64_t k = in_k[lbase + head];
-      if (k >= 0) {
-        sv = in_s[lbase + head];
-        sk = k;
-        sl = tid;
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double os = __shfl_xor(sv, o);
-      const int64_t ok = __shfl_xor(sk, o);
-      const int ol = __shfl_xor(sl, o);
-      if (ol >= 0 && (sl < 0 || os < sv || (os == sv && ok < sk))) {
-        sv = os;
-        sk = ok;
-        sl = ol;
-      }
-    }
-    const int buf = r & 1;
-    if ((tid & 63) == 0) {
-      t_s[buf][tid >> 6] = sv;
-      t_k[buf][tid >> 6] = sk;
-      t_l[buf][tid >> 6] = sl;
-    }
-    __syncthreads();
-    double bs = t_s[buf][0];
-    int64_t bk = t_k[buf][0];
-    int bl = t_l[buf][0];
+  // Bins are below 2^24 (plan limit), so they serve as int keys.
+  double cs[PF];
+  int ck[PF];
+  int64_t cq[PF];
+  int head = 0;  // records of this list already taken
+  auto fill = [&]() {
 #pragma unroll
-    for (int w = 1; w < kNT / 64; ++w) {
-      const int ol = t_l[buf][w];
-      if (ol >= 0 && (bl < 0 || t_s[buf][w] < bs || (t_s[buf][w] == bs && t_k[buf][w] < bk))) {
-        bs = t_s[buf][w];
-        bk = t_k[buf][w];
-        bl = ol;
+    for (int j = 0; j < PF; ++j) {
+      const int idx = head + j;
+      double sv = INFINITY;
+      int kv = INT_MAX;
+      int64_t qv = -1;
+      if (l < nl && idx < K) {
+        const int64_t kk = in_k[lbase + idx];
+        if (kk >= 0) {
+          sv = in_s[lbase + idx];
+          kv = (int)kk;
+          qv = in_q ? in_q[lbase + idx] : lbase + idx;
+        }
+      }
+      cs[j] = sv;
+      ck[j] = kv;
+      cq[j] = qv;
+    }
+  };
+  fill();
+  int nwin = 0;
+  for (int r = 0; r < K; ++r) {
+    const int hq = head & (PF - 1);
+    double sv = INFINITY;
+    int sk = INT_MAX;
+    int64_t sq = -1;
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      if (j == hq) {
+        sv = cs[j];
+        sk = ck[j];
+        sq = cq[j];
       }
     }
-    if (bl < 0) break;  // the same decision in every thread
-    if (bl == tid) {
-      const int64_t pos = lbase + head;
-      s_ws[r] = bs;
-      s_wk[r] = bk;
-      s_wq[r] = in_q ? in_q[pos] : pos;
+    const int own_k = sk;
+    wave_min_key(sv, sk);
+    if (!(sv < INFINITY)) break;  // the same decision in every lane of the wave
+    if (own_k == sk) {            // bins are distinct: this lane's list won
+      w_s[wv][r] = sv;
+      w_k[wv][r] = sk;
+      w_q[wv][r] = sq;
       ++head;
+      if ((head & (PF - 1)) == 0) fill();
     }
-    rounds = r + 1;
+    nwin = r + 1;
+  }
+  if (lane >= nwin && lane < K) {
+    w_s[wv][lane] = INFINITY;
+    w_k[wv][lane] = INT_MAX;
+    w_q[wv][lane] = -1;
   }
   __syncthreads();
+  bool wrote = false;
+  if (tid < (kNT / 64) * K) {
+    const int L = tid / K, pos = tid - L * K;
+    const double sv = w_s[L][pos];
+    const int sk = w_k[L][pos];
+    if (sv < INFINITY) {
+      int rank = pos;
+#pragma unroll
+      for (int L2 = 0; L2 < kNT / 64; ++L2) {
+        if (L2 == L) continue;
+        int a = 0, b = K;  // first index of list L2 whose key is not smaller
+        while (a < b) {
+          const int mid = (a + b) >> 1;
+          if (key_less(w_s[L2][mid], w_k[L2][mid], sv, sk)) a = mid + 1;
+          else b = mid;
+        }
+        rank += a;
+      }
+      if (rank < K) {
+        s_ws[rank] = sv;
+        s_wk[rank] = sk;
+        s_wq[rank] = w_q[L][pos];
+        wrote = true;
+      }
+    }
+  }
+  const int rounds = __syncthreads_count(wrote);
   double gmax = s_mx[0];
 #pragma unroll
   for (int w = 1; w < kNT / 64; ++w) gmax = s_mx[w] > gmax ? s_mx[w] : gmax;
