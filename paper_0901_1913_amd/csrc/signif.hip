@@ -79,6 +79,8 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
   __shared__ double w_s[kNT / 64][64];  // each wave's K best keys, in order
   __shared__ int w_i[kNT / 64][64];
   __shared__ int s_win[64];
+  __shared__ int c_slot[kNT / 64][kNT];  // each wave's candidate slots
+  __shared__ double s_sc[kSpan];         // ln p of the candidates
 
   const int tid = threadIdx.x;
   const int cw = blockIdx.y;
@@ -104,14 +106,13 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
 
   const int hp = hrow + 1;
   const int64_t k_first = k_lo > 1 ? k_lo : 1;
+  const int lane = tid & 63, wv = tid >> 6;
   double vmax = -INFINITY;
-  double ks[kBPT];
-  int ki[kBPT];
+  unsigned cand = 0;  // bit r: slot r * kNT + tid is a candidate
 #pragma unroll
   for (int r = 0; r < kBPT; ++r) {
     const int i = r * kNT + tid;
     const int64_t k = B0 - 1 + i;
-    double score = INFINITY;
     const bool owned = i >= 1 && i <= kOwn && k < nf;
     if (owned) {
       const uint8_t fl = s_fl[i];
@@ -120,10 +121,35 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
         const double v = (double)s_d[hrow][i];
         if (v > vmax) vmax = v;  // NaN never raises the maximum
         if (k <= nf - 2 && v > (double)s_d[hrow][i - 1] && v >= (double)s_d[hrow][i + 1])
-          score = log((double)k) + log_q_even(v, hp);
+          cand |= 1u << r;
       }
     }
-    ks[r] = score;
+  }
+  // ln p of the wave's candidates (about a third of the bins), evaluated by
+  // consecutive lanes: the wave's candidate slots are listed first, so the
+  // logarithms run on full waves instead of on every lane for every slot.
+  int ncand = 0;
+#pragma unroll
+  for (int r = 0; r < kBPT; ++r) {
+    const bool c = (cand >> r) & 1u;
+    const uint64_t m = __ballot(c);
+    const int below = (int)__builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (c) c_slot[wv][ncand + below] = r * kNT + tid;
+    ncand += __popcll(m);
+  }
+  __syncthreads();
+  for (int j = lane; j < ncand; j += 64) {
+    const int i = c_slot[wv][j];
+    s_sc[i] = log((double)(B0 - 1 + i)) + log_q_even((double)s_d[hrow][i], hp);
+  }
+  __syncthreads();
+  double ks[kBPT];
+  int ki[kBPT];
+#pragma unroll
+  for (int r = 0; r < kBPT; ++r) {
+    const int i = r * kNT + tid;
+    ks[r] = ((cand >> r) & 1u) ? s_sc[i] : INFINITY;
     ki[r] = i;
   }
   // Block maximum of the eligible Delta chi2 (for chi2_best).
@@ -151,7 +177,6 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
   // Tournament inside each wave: K rounds of wave arg-min over the threads'
   // heads (DPP permutations, no barrier); lane r keeps the r-th winner and
   // the winner's owner advances.  Every key of a wave is held by that wave.
-  const int lane = tid & 63, wv = tid >> 6;
   int head = 0;
   double my_s = INFINITY;
   int my_i = INT_MAX;
@@ -177,6 +202,7 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
     w_s[wv][lane] = my_s;
     w_i[wv][lane] = my_i;
   }
+  if (tid < K) s_win[tid] = -1;  // a slot no rank fills stays marked empty
   __syncthreads();
   // Merge of the sorted wave lists: a finite key's rank is its position in its
   // list plus the number of smaller keys in the other lists (keys are
@@ -209,10 +235,9 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
 
   const int64_t base = ((int64_t)cw * nblk + blockIdx.x) * K;
   if (tid < K) {
-    const bool ok = tid < rounds;
+    const bool ok = tid < rounds && s_win[tid] >= 0;
     const int i = ok ? s_win[tid] : 0;
-    rs[base + tid] = ok ? log((double)(B0 - 1 + i)) + log_q_even((double)s_d[hrow][i], hp)
-                        : INFINITY;
+    rs[base + tid] = ok ? s_sc[i] : INFINITY;
     rk[base + tid] = ok ? B0 - 1 + i : -1;
     rf[base + tid] = ok ? s_fl[i] : 0;
 #pragma unroll
@@ -321,6 +346,7 @@ __global__ __launch_bounds__(kNT) void k_top_merge(
     w_k[wv][lane] = INT_MAX;
     w_q[wv][lane] = -1;
   }
+  if (tid < K) s_wq[tid] = -1;  // a slot no rank fills stays marked empty
   __syncthreads();
   bool wrote = false;
   if (tid < (kNT / 64) * K) {
@@ -356,7 +382,7 @@ __global__ __launch_bounds__(kNT) void k_top_merge(
   if (!fin) {
     const int64_t ob = ((int64_t)cw * ng + g) * K;
     if (tid < K) {
-      const bool ok = tid < rounds;
+      const bool ok = tid < rounds && s_wq[tid] >= 0;
       o_s[ob + tid] = ok ? s_ws[tid] : INFINITY;
       o_k[ob + tid] = ok ? s_wk[tid] : -1;
       o_q[ob + tid] = ok ? s_wq[tid] : -1;
@@ -376,7 +402,7 @@ __global__ __launch_bounds__(kNT) void k_top_merge(
   }
   if (tid < K) {
     const int64_t o = (int64_t)c * K + tid;
-    if (tid < rounds) {
+    if (tid < rounds && s_wq[tid] >= 0) {
       const int64_t q = s_wq[tid];
       out.idx[o] = s_wk[tid];
       out.log_p[o] = s_ws[tid];
