@@ -297,6 +297,49 @@ def gradient_timing(steps):
             "schedule": schedule}
 
 
+def variants_timing(steps):
+    """The paper-faithful variants on the long workload: the search with floor
+    gridding (kernel_width = 1, Section 3b) and the cubic detrending."""
+    import torch
+    from paper_0901_1913_amd import fchi2 as F
+    from paper_0901_1913_amd import synth
+    cur = synth.make("long")
+    t = torch.from_numpy(cur.t).cuda()
+    x = torch.from_numpy(cur.x).cuda()
+    s = torch.from_numpy(cur.sigma).cuda()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision,
+                  kernel_width=1)
+    schedule = plan.autotune(t, x, s)
+    d, c0, fl = plan.search(t, x, s)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.search(t, x, s, dchi2=d, chi2_0=c0, flags=fl)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_floor = e0.elapsed_time(e1) / steps
+    xr = plan.detrend(t, x, s, 3)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.detrend(t, x, s, 3, x_out=xr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_det = e0.elapsed_time(e1) / steps
+    plan.close()
+    units = cur.n_freq * cur.H
+    log(f"variants (long): floor gridding {ms_floor:.4f} ms, cubic detrend {ms_det:.4f} ms")
+    return {"workload": "long", "floor_gridding_ms": round(ms_floor, 5),
+            "floor_gridding_value": round(units / (ms_floor * 1e-3), 1),
+            "floor_gridding_schedule": schedule,
+            "detrend_degree3_ms": round(ms_det, 5),
+            "detrend_points_per_s": round(cur.t.shape[0] / (ms_det * 1e-3), 1),
+            "unit": "freq*H/s"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,6 +354,8 @@ def main(argv=None):
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-multi", action="store_true",
                     help="skip the shared-alpha multi-source comparison")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the floor-gridding and detrending timings")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the adjoint timing on the diff workload")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -475,6 +520,8 @@ def main(argv=None):
         out["multi"] = multi_vs_curves(a.batched_steps)
     if not a.no_gradient:
         out["gradient"] = gradient_timing(a.steps)
+    if not a.no_variants:
+        out["variants"] = variants_timing(a.steps)
     print(json.dumps(out), flush=True)
     return 0
 

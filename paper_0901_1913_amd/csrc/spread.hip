@@ -32,16 +32,17 @@ namespace {
 
 constexpr int kNT = 256;
 
+// Sum over the block in a fixed order (wave butterflies, then the four wave
+// sums in order): deterministic, two barriers.  red holds kNT / 64 values.
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* red) {
   const int tid = threadIdx.x;
-  red[tid] = v;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
-  for (int s = kNT / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
   T r = red[0];
+#pragma unroll
+  for (int w = 1; w < kNT / 64; ++w) r += red[w];
   __syncthreads();
   return r;
 }
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(kNT) void k_moments_part(const double* __restrict__
                                                       const int64_t* __restrict__ off,
                                                       int bpc, int shared_t,
                                                       MomPart* __restrict__ part) {
-  __shared__ double red[kNT];
+  __shared__ double red[kNT / 64];
   __shared__ uint32_t bad_s;
   const int c = blockIdx.y;
   const int b = blockIdx.x;
