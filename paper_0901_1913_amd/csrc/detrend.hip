@@ -9,6 +9,9 @@
 // accumulates the Gram matrix G_jl = sum w P_j P_l and b_j = sum w x P_j in
 // FP64, solves G c = b by Cholesky (a pivot below 1e-12 of its diagonal is
 // dropped: too few points or a zero span), and writes x - sum c_j P_j(u).
+// Blocks have 256 threads, or 512 when the longest curve has 8192 points or
+// more (a single long curve is then spread over more lanes of its one CU;
+// 1024 would cap the registers at 128 and spill the small solve).
 #include <cmath>
 #include <cstdint>
 
@@ -19,8 +22,6 @@ namespace fchi2 {
 
 namespace {
 
-constexpr int kNT = 256;
-
 template <int NB>
 __device__ __forceinline__ void legendre(double u, double* P) {
   P[0] = 1.0;
@@ -30,7 +31,7 @@ __device__ __forceinline__ void legendre(double u, double* P) {
     P[j + 1] = ((double)(2 * j + 1) * u * P[j] - (double)j * P[j - 1]) / (double)(j + 1);
 }
 
-template <int D>
+template <int D, int kNT>
 __global__ __launch_bounds__(kNT) void k_detrend(const double* __restrict__ t,
                                                  const double* __restrict__ x,
                                                  const double* __restrict__ sigma,
@@ -143,20 +144,29 @@ __global__ __launch_bounds__(kNT) void k_detrend(const double* __restrict__ t,
   }
 }
 
-}  // namespace
-
-hipError_t launch_detrend(const double* t, const double* x, const double* sigma,
-                          const int64_t* offsets, int n_curves, int degree, double* x_out,
-                          double* coef, hipStream_t st) {
+template <int NT>
+hipError_t detrend_nt(const double* t, const double* x, const double* sigma,
+                      const int64_t* offsets, int n_curves, int degree, double* x_out,
+                      double* coef, hipStream_t st) {
   dim3 gr((unsigned)n_curves);
   switch (degree) {
-    case 0: hipLaunchKernelGGL(k_detrend<0>, gr, dim3(kNT), 0, st, t, x, sigma, offsets, x_out, coef); break;
-    case 1: hipLaunchKernelGGL(k_detrend<1>, gr, dim3(kNT), 0, st, t, x, sigma, offsets, x_out, coef); break;
-    case 2: hipLaunchKernelGGL(k_detrend<2>, gr, dim3(kNT), 0, st, t, x, sigma, offsets, x_out, coef); break;
-    case 3: hipLaunchKernelGGL(k_detrend<3>, gr, dim3(kNT), 0, st, t, x, sigma, offsets, x_out, coef); break;
+    case 0: hipLaunchKernelGGL((k_detrend<0, NT>), gr, dim3(NT), 0, st, t, x, sigma, offsets, x_out, coef); break;
+    case 1: hipLaunchKernelGGL((k_detrend<1, NT>), gr, dim3(NT), 0, st, t, x, sigma, offsets, x_out, coef); break;
+    case 2: hipLaunchKernelGGL((k_detrend<2, NT>), gr, dim3(NT), 0, st, t, x, sigma, offsets, x_out, coef); break;
+    case 3: hipLaunchKernelGGL((k_detrend<3, NT>), gr, dim3(NT), 0, st, t, x, sigma, offsets, x_out, coef); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_detrend(const double* t, const double* x, const double* sigma,
+                          const int64_t* offsets, int n_curves, int degree, int64_t max_n,
+                          double* x_out, double* coef, hipStream_t st) {
+  if (max_n >= 8192)
+    return detrend_nt<512>(t, x, sigma, offsets, n_curves, degree, x_out, coef, st);
+  return detrend_nt<256>(t, x, sigma, offsets, n_curves, degree, x_out, coef, st);
 }
 
 }  // namespace fchi2

@@ -1085,8 +1085,8 @@ fchi2_status_t fchi2_detrend(fchi2_plan_t plan, const double* t, const double* x
   if (!t || !x || !sigma || !x_out)
     return fail(FCHI2_ERR_ARG, "t, x, sigma and x_out must not be NULL");
   if (degree < 0 || degree > 3) return fail(FCHI2_ERR_ARG, "degree must be in 0..3");
-  hipError_t e = launch_detrend(t, x, sigma, plan->d_off, plan->desc.n_curves, degree, x_out,
-                                coef, (hipStream_t)stream);
+  hipError_t e = launch_detrend(t, x, sigma, plan->d_off, plan->desc.n_curves, degree,
+                                plan->max_n, x_out, coef, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "detrend");
   return FCHI2_OK;
 }

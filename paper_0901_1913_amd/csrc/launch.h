@@ -123,8 +123,8 @@ hipError_t launch_top_merge(const Moments* mom, const Geom& g, int curve0, int n
 // Subtract each curve's weighted least-squares polynomial of the given degree
 // (0..3) in t; coef (nullable) receives its Legendre coefficients in u.
 hipError_t launch_detrend(const double* t, const double* x, const double* sigma,
-                          const int64_t* offsets, int n_curves, int degree, double* x_out,
-                          double* coef, hipStream_t st);
+                          const int64_t* offsets, int n_curves, int degree, int64_t max_n,
+                          double* x_out, double* coef, hipStream_t st);
 
 // Fine search on the ungridded points around given centre frequencies.
 struct FineOut {
