@@ -24,12 +24,14 @@
 // Phase 1 (fused with the per-bin solve): one block of 256 threads solves
 // 1024 consecutive bins, the first and last being halo bins whose values only
 // serve the neighbour test, keeps all H rows in LDS and selects the K best of
-// its 1022 owned bins by a tournament: each thread keeps its four keys
-// (ln p, k) sorted, and each round takes the block minimum of the threads'
-// heads (wave shuffles, one barrier); the owner of the winner advances.  The
-// K winners are written in order.  Phase 2: the sorted per-block lists are
-// merged in groups of up to 256 (one list per thread, the same tournament),
-// and the group lists once more per curve, which gives the final K.
+// its 1022 owned bins: ln p is evaluated once per candidate on consecutive
+// lanes, each thread keeps its four keys (ln p, k) sorted, each wave runs a
+// tournament (K rounds of a wave arg-min over the threads' heads by DPP lane
+// permutations, the owner of the winner advancing), and the four sorted wave
+// lists are merged by rank.  The K winners are written in order.  Phase 2:
+// the sorted per-block lists are merged in groups of up to 256 (one list per
+// thread, the same wave tournaments and rank merge), and the group lists once
+// more per curve, which gives the final K.
 #include <cmath>
 #include <cstdint>
 

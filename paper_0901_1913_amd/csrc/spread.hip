@@ -17,7 +17,9 @@
 // Two real grids are packed per complex grid (real part, imaginary part);
 // each workgroup owns a tile of cells of one packed grid and sums the kernel
 // contributions of its points cell by cell (deterministic, no atomics).  The
-// arithmetic is FP64; the grid is stored as S (float for mixed plans).
+// arithmetic is FP64 (for float grids the kernel's exponential is taken to
+// FP32 accuracy, see es_kernel.h); the grid is stored as S (float for mixed
+// plans).
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
