@@ -366,8 +366,9 @@ fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* 
 /*
  * Autotuner.  Times every candidate schedule of the plan on the caller's data
  * (the FFT digit splits with the fewest passes and the most balanced splits
- * with one pass more, spreading tiles of 1024 to
- * 8192 cells, and waves of wave_max, wave_max/2, wave_max/4 curves) with HIP
+ * with one pass more, for FP32 grids each on FFT tiles of 4096 or 8192
+ * elements per pass, spreading tiles of 1024 to 8192 cells, and waves of
+ * wave_max, wave_max/2, wave_max/4 curves) with HIP
  * events on `stream` (two timed runs each after a warm-up, then the three
  * fastest five more times each, in turns), keeps the fastest in the plan,
  * and appends it to the
@@ -386,7 +387,8 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
 /*
  * Current schedule of a plan: info[0] = FFT passes, info[1..4] = log2 radix of
  * digits 1..4 (0 if unused), info[5] = log2 spreading tile, info[6] = curves
- * per wave, info[7] = kernel width.  n must be >= 8.
+ * per wave, info[7] = kernel width, and with n >= 12 info[8..11] = log2 FFT
+ * tile elements of passes 1..4 (0 if unused).  n must be >= 8.
  */
 fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n);
 

@@ -123,6 +123,7 @@ enum PassMode : int { MODE_FWD = 0, MODE_BWD = 1 };
 struct FftPlan {
   int np;                       // number of passes
   int logn[kMaxPasses + 1];     // logn[q] = log2 N_q, digit q = 1 (least significant)..np
+  int le[kMaxPasses + 1];       // log2 of pass q's tile (N_q rows x 2^(le - logn) columns)
   int logL;
 };
 

@@ -112,9 +112,15 @@ __device__ __forceinline__ void dft_reg(cplx<R>* v) {
   dit_stages<R, N, 1>(v);
 }
 
-constexpr int kNT = 256;  // threads per FFT workgroup
-constexpr int kLE = 12;   // log2 of the tile: 4096 complex elements
-constexpr int kEPT = (1 << kLE) / kNT;  // elements per thread (16)
+// A tile holds 2^12 complex elements, or 2^13 with FP32 grids (the same LDS
+// bytes as an FP64 tile of 2^12; twice the columns, so runs twice as long):
+// the plan chooses per pass.  Every thread holds kEPT elements, so a
+// workgroup has 256 or 512 threads.
+constexpr int kEPT = 16;  // elements per thread
+template <typename S>
+constexpr int tile_log_max() {
+  return sizeof(S) == 4 ? 13 : 12;
+}
 using C = cplx<double>;
 
 // Grid data each pass touches once.  Runs of at least 128 bytes (NT) are
@@ -149,22 +155,24 @@ __device__ __forceinline__ cplx<S> narrow(C v) {
   return cmk<S>((S)v.x, (S)v.y);
 }
 
-// Stockham stage geometry over a tile of N rows x T columns.  Butterfly bi of
-// thread tid (slot it) is bi = tid + it * kNT: column c = bi % T, butterfly
+// Stockham stage geometry over a tile of N rows x T columns, NT = N T / kEPT
+// threads.  Butterfly bi of thread tid (slot it) is bi = tid + it * NT:
+// column c = bi % T, butterfly
 // b = bi / T; its element i is input row b + i N / RAD and output row
 // (b / NS) NS RAD + b % NS + i NS.  Every thread holds kEPT elements.
 template <int LOGN, int LOGT, int LOGNS>
 struct Stage {
   static constexpr int N = 1 << LOGN;
   static constexpr int T = 1 << LOGT;
+  static constexpr int NT = (N * T) / kEPT;
   static constexpr int LOGRAD = (LOGN - LOGNS) >= 4 ? 4 : (LOGN - LOGNS);
   static constexpr int RAD = 1 << LOGRAD;
   static constexpr int NS = 1 << LOGNS;
   static constexpr int PER = kEPT / RAD;
   static constexpr bool LAST = (LOGNS + LOGRAD) == LOGN;
   static_assert(PER * RAD == kEPT, "radix must divide the per-thread elements");
-  __device__ static int col(int tid, int it) { return (tid + it * kNT) & (T - 1); }
-  __device__ static int bfly(int tid, int it) { return (tid + it * kNT) >> LOGT; }
+  __device__ static int col(int tid, int it) { return (tid + it * NT) & (T - 1); }
+  __device__ static int bfly(int tid, int it) { return (tid + it * NT) >> LOGT; }
   __device__ static int in_row(int b, int i) { return b + i * (N / RAD); }
   __device__ static int out_row(int b, int i) {
     return ((b >> LOGNS) << (LOGNS + LOGRAD)) + (b & (NS - 1)) + i * NS;
@@ -239,9 +247,9 @@ __device__ __forceinline__ C root(int64_t e, int logM) {
 //   PASS_FIRST, np >= 3: w_M^{jd k}        (jd fixed for the tile)   = r[k]
 //   PASS_FIRST, np == 2: w_L^{(g0+cc) k}   = r[k] * small[cc k]
 //   PASS_MID:            w_M^{jd (K0+cc+Tail k)}                     = c[cc] r[k]
-// with r, c built per workgroup in FP64 and small[e] = w_L^e, e < 2^kLE.
+// with r, c built per workgroup in FP64 and small[e] = w_L^e, e < N T.
 template <typename S, int LOGN, int LOGT>
-__global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<S>* in,
+__global__ __launch_bounds__(((1 << LOGN) << LOGT) / kEPT) void k_fft_pass(FftPassArgs a, const cplx<S>* in,
                                                  cplx<S>* out,
                                                  const Moments* __restrict__ mom, Geom g,
                                                  const C* __restrict__ tw_stage,
@@ -249,7 +257,8 @@ __global__ __launch_bounds__(kNT) void k_fft_pass(FftPassArgs a, const cplx<S>* 
   constexpr int N = 1 << LOGN;
   constexpr int T = 1 << LOGT;
   constexpr int PT = (T == 1) ? 1 : T + 1;
-  static_assert(N * T == (1 << kLE), "tile size");
+  constexpr int kNT = (N * T) / kEPT;  // threads of this tile
+  static_assert(N * T == 4096 || (N * T == 8192 && sizeof(S) == 4), "tile size");
   constexpr bool NT = T * sizeof(cplx<S>) >= 128;
   using S0 = Stage<LOGN, LOGT, 0>;
   using SL = Stage<LOGN, LOGT, last_logns(LOGN)>;
@@ -429,7 +438,7 @@ hipError_t launch_one(const FftPassArgs& a, const void* in, void* out, const Mom
                       const Geom& g, const void* tws, const void* twsm, int n_curves,
                       int64_t ncols, hipStream_t st) {
   dim3 grid((unsigned)(ncols >> LOGT), (unsigned)g.P, (unsigned)n_curves);
-  hipLaunchKernelGGL((k_fft_pass<S, LOGN, LOGT>), grid, dim3(kNT), 0, st, a,
+  hipLaunchKernelGGL((k_fft_pass<S, LOGN, LOGT>), grid, dim3(((1 << LOGN) << LOGT) / kEPT), 0, st, a,
                      (const cplx<S>*)in, (cplx<S>*)out, mom, g, (const C*)tws, (const C*)twsm);
   return hipGetLastError();
 }
@@ -439,24 +448,41 @@ hipError_t dispatch(const FftPassArgs& a, int logn, int logt, const void* in, vo
                     const Moments* mom, const Geom& g, const void* tws, const void* twsm,
                     int n_curves, int64_t ncols, hipStream_t st) {
   if (logt == 0) {
-    if (logn == kLE) return launch_one<S, kLE, 0>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+    if (logn == 12) return launch_one<S, 12, 0>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+    if constexpr (tile_log_max<S>() == 13)
+      if (logn == 13) return launch_one<S, 13, 0>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
     return hipErrorInvalidValue;
   }
-  if (logn + logt != kLE) return hipErrorInvalidValue;
-  switch (logn) {
-    case 4: return launch_one<S, 4, kLE - 4>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
-    case 5: return launch_one<S, 5, kLE - 5>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
-    case 6: return launch_one<S, 6, kLE - 6>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
-    case 7: return launch_one<S, 7, kLE - 7>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
-    case 8: return launch_one<S, 8, kLE - 8>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
-    case 9: return launch_one<S, 9, kLE - 9>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
-    default: return hipErrorInvalidValue;
+  if (logn + logt == 12) {
+    switch (logn) {
+      case 4: return launch_one<S, 4, 8>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+      case 5: return launch_one<S, 5, 7>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+      case 6: return launch_one<S, 6, 6>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+      case 7: return launch_one<S, 7, 5>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+      case 8: return launch_one<S, 8, 4>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+      case 9: return launch_one<S, 9, 3>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+      default: return hipErrorInvalidValue;
+    }
   }
+  if constexpr (tile_log_max<S>() == 13) {
+    if (logn + logt == 13) {
+      switch (logn) {
+        case 4: return launch_one<S, 4, 9>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+        case 5: return launch_one<S, 5, 8>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+        case 6: return launch_one<S, 6, 7>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+        case 7: return launch_one<S, 7, 6>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+        case 8: return launch_one<S, 8, 5>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+        case 9: return launch_one<S, 9, 4>(a, in, out, mom, g, tws, twsm, n_curves, ncols, st);
+        default: return hipErrorInvalidValue;
+      }
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int fft_tile_log() { return kLE; }
+int fft_tile_log(bool fp64) { return fp64 ? tile_log_max<double>() : tile_log_max<float>(); }
 
 hipError_t launch_fft_pass(bool fp64, const FftPassArgs& a, int logn, int logt, const void* in,
                            void* out, const Moments* mom, const Geom& g, const void* tws,

@@ -90,6 +90,7 @@ bool plan_fft(int logL, int LE, FftPlan& fp) {
     if (logL < 12) return false;
     fp.np = 1;
     fp.logn[1] = logL;
+    fp.le[1] = logL;
     fp.logL = logL;
     return true;
   }
@@ -132,7 +133,10 @@ bool plan_fft(int logL, int LE, FftPlan& fp) {
     }
     if (best_min >= 0) {
       fp.np = np;
-      for (int q = 1; q <= np; ++q) fp.logn[q] = best[q];
+      for (int q = 1; q <= np; ++q) {
+        fp.logn[q] = best[q];
+        fp.le[q] = LE;
+      }
       fp.logL = logL;
       return true;
     }
@@ -146,7 +150,7 @@ bool plan_fft(int logL, int LE, FftPlan& fp) {
 // (columns per tile) give longer contiguous runs: at L = 2^18 the two-pass
 // split 2^9 x 2^9 moves runs of 8 elements (64 B), three passes of 2^6 move
 // runs of 64.
-std::vector<FftPlan> fft_splits(int logL, int LE) {
+std::vector<FftPlan> fft_splits_uniform(int logL, int LE) {
   std::vector<FftPlan> out;
   FftPlan best{};
   if (!plan_fft(logL, LE, best)) return out;
@@ -182,7 +186,10 @@ std::vector<FftPlan> fft_splits(int logL, int LE) {
       FftPlan f{};
       f.np = np;
       f.logL = logL;
-      for (int q = 1; q <= np; ++q) f.logn[q] = ln[q];
+      for (int q = 1; q <= np; ++q) {
+        f.logn[q] = ln[q];
+        f.le[q] = LE;
+      }
       if (np == best.np) {
         out.push_back(f);
       } else if (mn >= best_min) {
@@ -192,6 +199,50 @@ std::vector<FftPlan> fft_splits(int logL, int LE) {
       }
     }
     out.insert(out.end(), found.begin(), found.end());
+  }
+  return out;
+}
+
+// Whether every pass q of the split fits its tile of 2^le[q] elements: the
+// T = 2^(le[q] - logn[q]) columns of a tile must share their other digits.
+bool split_valid(const FftPlan& f) {
+  if (f.np == 1) return true;
+  const int np = f.np;
+  for (int q = 1; q <= np; ++q)
+    if (f.le[q] - f.logn[q] < 0) return false;
+  if (f.le[np] - f.logn[np] > f.logn[1]) return false;  // first pass
+  for (int q = 2; q < np; ++q) {                          // middle passes
+    int tail = 0;
+    for (int d = q + 1; d <= np; ++d) tail += f.logn[d];
+    if (f.le[q] - f.logn[q] > tail) return false;
+  }
+  return f.le[1] - f.logn[1] <= f.logL - f.logn[1];      // last pass
+}
+
+// Autotuner candidates: the splits of fft_splits_uniform for 2^12-element
+// tiles and, for FP32 grids, for 2^13-element tiles (twice the columns, so
+// runs twice as long), each also tried with its first pass on the smaller
+// tile (that pass reads the sparse spread grid and writes whole columns).
+std::vector<FftPlan> fft_splits(int logL, bool fp64) {
+  std::vector<FftPlan> base = fft_splits_uniform(logL, 12);
+  if (fp64 || logL <= 13) return base;
+  for (const FftPlan& f : fft_splits_uniform(logL, 13)) base.push_back(f);
+  std::vector<FftPlan> out;
+  auto add = [&](const FftPlan& f) {
+    if (!split_valid(f)) return;
+    for (const FftPlan& g : out) {
+      bool same = g.np == f.np;
+      for (int q = 1; q <= f.np && same; ++q) same = g.logn[q] == f.logn[q] && g.le[q] == f.le[q];
+      if (same) return;
+    }
+    out.push_back(f);
+  };
+  for (const FftPlan& f : base) {
+    for (int v = 0; v < 3; ++v) {  // all 2^12 tiles, all 2^13, first pass 2^12 and the rest 2^13
+      FftPlan g = f;
+      for (int q = 1; q <= g.np; ++q) g.le[q] = (v == 0 || (v == 2 && q == g.np)) ? 12 : 13;
+      add(g);
+    }
   }
   return out;
 }
@@ -280,7 +331,6 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
                            const Geom* geom = nullptr) {
   const Geom& g = geom ? *geom : pl->g;
   const FftPlan& fp = pl->fp;
-  const int LE = fft_tile_log();
   FftPassArgs a{};
   a.mode = mode;
   a.np = fp.np;
@@ -303,7 +353,7 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
     a.q = q;
     a.kind = (q == fp.np) ? PASS_FIRST : (q == 1 ? PASS_LAST : PASS_MID);
     const int logn = fp.logn[q];
-    const int logt = LE - logn;
+    const int logt = fp.le[q] - logn;
     const int64_t ncols = g.L >> logn;
     const void* in = (q == fp.np) ? gA : gB;
     void* out = gB;
@@ -668,7 +718,7 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     }
   }
   const int logL = ilog2(g.L);
-  if (!plan_fft(logL, fft_tile_log(), pl->fp)) {
+  if (!plan_fft(logL, 12, pl->fp)) {
     delete pl;
     return fail(FCHI2_ERR_UNSUPPORTED, "no FFT pass split for L = 2^%d", logL);
   }
@@ -729,7 +779,7 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     return hipMalloc(p, bytes) == hipSuccess;
   };
   const int LT = 1 << kStageLog;
-  const int64_t NSM = (int64_t)1 << fft_tile_log();
+  const int64_t NSM = (int64_t)1 << fft_tile_log(pl->fp64);
   const int n_gl = 128;
   if (!dev_alloc((void**)&pl->d_off, sizeof(int64_t) * (d.n_curves + 1)) ||
       !dev_alloc(&pl->d_tw_stage, 16 * (size_t)LT) ||
@@ -1055,7 +1105,7 @@ fchi2_status_t fchi2_autotune_multi(fchi2_plan_t plan, const double* t, const do
     (void)hipGraphExecDestroy(pl->gexec);
     pl->gexec = nullptr;
   }
-  const std::vector<FftPlan> splits = fft_splits(pl->fp.logL, fft_tile_log());
+  const std::vector<FftPlan> splits = fft_splits(pl->fp.logL, pl->fp64);
   const std::vector<int> waves = {pl->wave};
   const bool prof = pl->prof;
   pl->prof = false;
@@ -1141,12 +1191,12 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
   snprintf(key, sizeof key, "gfx950 H=%d nf=%lld prec=%d w=%d curves=2^%d maxn=2^%d wavemax=%d",
            pl->g.H, (long long)pl->g.n_freq, pl->fp64 ? 0 : 1, pl->g.w, lg_nc, lg_n,
            pl->wave_max);
-  const std::vector<FftPlan> splits = fft_splits(pl->fp.logL, fft_tile_log());
-  auto apply = [&](const int* ln, int np, int tile, int wave) -> bool {
+  const std::vector<FftPlan> splits = fft_splits(pl->fp.logL, pl->fp64);
+  auto apply = [&](const int* ln, const int* le, int np, int tile, int wave) -> bool {
     for (const FftPlan& f : splits) {
       if (f.np != np) continue;
       bool same = true;
-      for (int q = 1; q <= np; ++q) same = same && f.logn[q] == ln[q];
+      for (int q = 1; q <= np; ++q) same = same && f.logn[q] == ln[q] && f.le[q] == le[q];
       if (!same) continue;
       pl->log_tile = tile;
       pl->wave = wave;
@@ -1167,11 +1217,11 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
       while (!found && fgets(line, sizeof line, fh)) {
         const char* tag = strstr(line, " | ");
         if (!tag || strncmp(line, key, strlen(key)) != 0 || line + strlen(key) != tag) continue;
-        int np = 0, ln[kMaxPasses + 1] = {0}, tile = 0, wave = 0;
-        if (sscanf(tag, " | np=%d fft=%d,%d,%d,%d tile=%d wave=%d", &np, &ln[1], &ln[2], &ln[3],
-                   &ln[4], &tile, &wave) == 7 &&
+        int np = 0, ln[kMaxPasses + 1] = {0}, le[kMaxPasses + 1] = {0}, tile = 0, wave = 0;
+        if (sscanf(tag, " | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d", &np, &ln[1],
+                   &ln[2], &ln[3], &ln[4], &le[1], &le[2], &le[3], &le[4], &tile, &wave) == 11 &&
             tile >= 10 && tile <= 13 && wave >= 1 && wave <= pl->wave_max)
-          found = apply(ln, np, tile, wave);
+          found = apply(ln, le, np, tile, wave);
       }
       fclose(fh);
       if (found) return FCHI2_OK;
@@ -1204,9 +1254,10 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
   if (res != FCHI2_OK) return res;
   if (cache_path) {
     if (FILE* fh = fopen(cache_path, "a")) {
-      fprintf(fh, "%s | np=%d fft=%d,%d,%d,%d tile=%d wave=%d ms=%.4f\n", key, best_f.np,
-              best_f.logn[1], best_f.logn[2], best_f.logn[3], best_f.logn[4], best_tile,
-              best_wave, best_ms);
+      fprintf(fh, "%s | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d ms=%.4f\n", key,
+              best_f.np, best_f.logn[1], best_f.logn[2], best_f.logn[3], best_f.logn[4],
+              best_f.le[1], best_f.le[2], best_f.le[3], best_f.le[4], best_tile, best_wave,
+              best_ms);
       fclose(fh);
     }
   }
@@ -1221,6 +1272,7 @@ fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n) {
   info[5] = plan->log_tile;
   info[6] = plan->wave;
   info[7] = plan->g.w;
+  for (int q = 1; q <= kMaxPasses && 7 + q < n; ++q) info[7 + q] = q <= plan->fp.np ? plan->fp.le[q] : 0;
   return FCHI2_OK;
 }
 
@@ -1231,7 +1283,7 @@ void fchi2_destroy(fchi2_plan_t plan) {
   if (plan->d_off) (void)hipFree(plan->d_off);
   if (plan->d_tw_stage) (void)hipFree(plan->d_tw_stage);
   if (plan->d_tw_small) (void)hipFree(plan->d_tw_small);
-  if (plan->d_D) hipFree(plan->d_D);
+  if (plan->d_D) (void)hipFree(plan->d_D);
   if (plan->d_gl) (void)hipFree(plan->d_gl);
   delete plan;
 }

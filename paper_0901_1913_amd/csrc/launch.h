@@ -35,9 +35,9 @@ hipError_t launch_spread(bool fp64, const double* t, const double* x, const doub
                          bool share_tb = false);
 size_t tile_bounds_bytes(const Geom& g, int log_tile, int n_curves);
 
-// log2 of the elements of one FFT tile (rows x columns held in LDS).
-int fft_tile_log();
-// tws: omega_{2^13}^e (FP64), twsm: omega_L^e for e < 2^fft_tile_log() (FP64).
+// log2 of the elements of the largest FFT tile (rows x columns held in LDS).
+int fft_tile_log(bool fp64);
+// tws: omega_{2^13}^e (FP64), twsm: omega_L^e for e < 2^fft_tile_log(fp64) (FP64).
 hipError_t launch_fft_pass(bool fp64, const FftPassArgs& a, int logn, int logt, const void* in,
                            void* out, const Moments* mom, const Geom& g, const void* tws,
                            const void* twsm, int n_curves, int64_t ncols, hipStream_t st);

@@ -494,10 +494,11 @@ class Plan:
 
     def info(self) -> dict:
         """The plan's schedule: FFT radices, spreading tile, wave, kernel width."""
-        arr = (ctypes.c_int32 * 8)()
-        _check(lib().fchi2_plan_info(self._h, arr, 8))
+        arr = (ctypes.c_int32 * 12)()
+        _check(lib().fchi2_plan_info(self._h, arr, 12))
         np_ = int(arr[0])
         return {"fft_log_radices": [int(arr[q]) for q in range(1, np_ + 1)],
+                "fft_log_tiles": [int(arr[7 + q]) for q in range(1, np_ + 1)],
                 "spread_tile": 1 << int(arr[5]), "curves_per_wave": int(arr[6]),
                 "kernel_width": int(arr[7])}
 
