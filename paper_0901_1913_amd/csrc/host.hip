@@ -744,7 +744,7 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     max_n = n > max_n ? n : max_n;
   }
   pl->max_n = max_n;
-  pl->mom_bpc = (int)std::min<int64_t>(256, std::max<int64_t>(1, (max_n + 4095) / 4096));
+  pl->mom_bpc = (int)std::min<int64_t>(256, std::max<int64_t>(1, (max_n + 1023) / 1024));
   size_t off = 0;
   pl->off_mom = off;
   off = align256(off + sizeof(Moments) * (size_t)d.n_curves);

@@ -104,31 +104,48 @@ __global__ __launch_bounds__(kNT) void k_moments_part(const double* __restrict__
   }
 }
 
-// Phase 2: one thread per curve combines the chunks in order (parallel
-// variance update) and writes the curve's Moments and chi2_0.
-__global__ __launch_bounds__(kNT) void k_moments_fin(const double* __restrict__ t,
-                                                     const int64_t* __restrict__ off,
-                                                     int n_curves, int bpc, int shared_t,
-                                                     const double* __restrict__ scale,
-                                                     const MomPart* __restrict__ part, Geom g,
-                                                     Moments* __restrict__ mom,
-                                                     double* __restrict__ chi2_out) {
-  const int c = blockIdx.x * kNT + threadIdx.x;
-  if (c >= n_curves) return;
-  const int64_t a = shared_t ? off[0] : off[c], e = shared_t ? off[1] : off[c + 1];
-  const int64_t n = e - a;
+// Pairwise combination of two chunk summaries (parallel variance update);
+// an empty chunk (W = 0) leaves the other unchanged.
+__device__ __forceinline__ void mom_combine(double& W, double& mean, double& M2, double W2,
+                                            double mean2, double M22) {
+  if (!(W2 > 0.0)) return;
+  const double Wn = W + W2;
+  const double dlt = mean2 - mean;
+  mean += dlt * (W2 / Wn);
+  M2 += M22 + dlt * dlt * (W * W2 / Wn);
+  W = Wn;
+}
+
+// Phase 2: one wave per curve.  Lane j combines chunks j, j + 64, ... in
+// order, then the 64 lane summaries are combined by a fixed pairwise tree
+// (deterministic); lane 0 writes the curve's Moments and chi2_0.
+__global__ __launch_bounds__(64) void k_moments_fin(const double* __restrict__ t,
+                                                    const int64_t* __restrict__ off,
+                                                    int n_curves, int bpc, int shared_t,
+                                                    const double* __restrict__ scale,
+                                                    const MomPart* __restrict__ part, Geom g,
+                                                    Moments* __restrict__ mom,
+                                                    double* __restrict__ chi2_out) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
   double W = 0.0, mean = 0.0, M2 = 0.0;
   uint32_t fl = 0;
-  for (int b = 0; b < bpc; ++b) {
+  for (int b = lane; b < bpc; b += 64) {
     const MomPart pp = part[(int64_t)c * bpc + b];
     fl |= pp.bad;
-    if (!(pp.W > 0.0)) continue;
-    const double Wn = W + pp.W;
-    const double dlt = pp.mean - mean;
-    mean += dlt * (pp.W / Wn);
-    M2 += pp.M2 + dlt * dlt * (W * pp.W / Wn);
-    W = Wn;
+    mom_combine(W, mean, M2, pp.W, pp.mean, pp.M2);
   }
+  for (int o = 1; o < 64; o <<= 1) {
+    const double W2 = __shfl_down(W, o), mean2 = __shfl_down(mean, o), M22 = __shfl_down(M2, o);
+    const uint32_t f2 = (uint32_t)__shfl_down((int)fl, o);
+    if ((lane & (2 * o - 1)) == 0) {
+      mom_combine(W, mean, M2, W2, mean2, M22);
+      fl |= f2;
+    }
+  }
+  if (lane != 0) return;
+  const int64_t a = shared_t ? off[0] : off[c], e = shared_t ? off[1] : off[c + 1];
+  const int64_t n = e - a;
   Moments m;
   m.W = W;
   m.xbar = mean;
@@ -407,8 +424,8 @@ hipError_t launch_moments(const double* t, const double* x, const double* sigma,
                      offsets, bpc, shared_t ? 1 : 0, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_moments_fin, dim3((n_curves + kNT - 1) / kNT), dim3(kNT), 0, st, t,
-                     offsets, n_curves, bpc, shared_t ? 1 : 0, scale, part, g, mom, chi2_0);
+  hipLaunchKernelGGL(k_moments_fin, dim3(n_curves), dim3(64), 0, st, t, offsets, n_curves, bpc,
+                     shared_t ? 1 : 0, scale, part, g, mom, chi2_0);
   return hipGetLastError();
 }
 
