@@ -366,8 +366,8 @@ def main(argv=None):
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for {max(a.gpus, world)}); the search "
-              "shards by curves or frequency bands across GPUs, which this build does not "
-              "run.", file=sys.stderr)
+              "would shard by curves or frequency bands across GPUs, and no multi-GPU "
+              "path is implemented.", file=sys.stderr)
         return 2
 
     import torch
