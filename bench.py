@@ -111,6 +111,11 @@ def cpu_baseline(cur, budget_s, seed=7):
     t0 = time.perf_counter()
     _oracle_chunk((t, x, s, probe * (cur.f_max / nf), cur.H))
     per_bin = max(time.perf_counter() - t0, 1e-4)
+    # One core on its own: a short run of consecutive bins in this process.
+    one = np.arange(1, 33, dtype=np.int64) * (nf // 64)
+    t0 = time.perf_counter()
+    _oracle_chunk((t, x, s, one * (cur.f_max / nf), cur.H))
+    one_core = len(one) * cur.H / (time.perf_counter() - t0)
     n_bins = int(max(cores, min(4096, budget_s * cores / per_bin)))
     n_bins = (n_bins // cores) * cores
     bins = np.sort(rng.choice(np.arange(1, nf), size=n_bins, replace=False))
@@ -121,7 +126,7 @@ def cpu_baseline(cur, budget_s, seed=7):
         parts = pool.map(_oracle_chunk, [(t, x, s, c * (cur.f_max / nf), cur.H) for c in chunks])
     el = time.perf_counter() - t0
     return (bins, np.concatenate([p[0] for p in parts], axis=1),
-            np.concatenate([p[1] for p in parts]), el, cores)
+            np.concatenate([p[1] for p in parts]), el, cores, one_core)
 
 
 def batched_vs_plain(steps):
@@ -496,12 +501,15 @@ def main(argv=None):
     if not a.no_cpu_baseline:
         from oracle import fchi2_oracle as ora
         log("oracle CPU baseline ...")
-        bins, d_ora, kappa, el, cores = cpu_baseline(cur, a.cpu_seconds)
+        bins, d_ora, kappa, el, cores, one_core = cpu_baseline(cur, a.cpu_seconds)
+        v_cpu = len(bins) * cur.H / el
         out["cpu_baseline"] = {
-            "value": round(len(bins) * cur.H / el, 2), "unit": "freq*H/s", "cores": cores,
+            "value": round(v_cpu, 2), "unit": "freq*H/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{len(bins)} seeded random bins of the {a.workload} workload "
-                      f"(all H'=1..{cur.H}), {el:.1f} s wall"}
+                      f"(all H'=1..{cur.H}), {el:.1f} s wall",
+            "one_core_value": round(one_core, 2),
+            "full_grid_s_extrapolated": round(units / v_cpu, 1)}
         span = float(cur.t[-1] - cur.t[0])
         freqs = bins * (cur.f_max / cur.n_freq)
         err = ora.rel_err(d_gpu[:, bins], d_ora)
