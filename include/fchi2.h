@@ -55,7 +55,7 @@ typedef struct fchi2_plan_s* fchi2_plan_t;
 typedef enum {
   FCHI2_OK = 0,
   FCHI2_ERR_ARG = 1,          /* invalid argument (message says which)       */
-  FCHI2_ERR_NOMEM = 2,        /* plan-table allocation failed                */
+  FCHI2_ERR_NOMEM = 2,        /* plan tables: out of device memory           */
   FCHI2_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed  */
   FCHI2_ERR_STATE = 4,        /* call not valid for this plan's flags/state  */
   FCHI2_ERR_UNSUPPORTED = 5   /* size or parameter outside what is built     */

@@ -775,8 +775,10 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     fchi2_destroy(pl);
     return s;
   };
+  hipError_t alloc_err = hipSuccess;
   auto dev_alloc = [&](void** p, size_t bytes) -> bool {
-    return hipMalloc(p, bytes) == hipSuccess;
+    alloc_err = hipMalloc(p, bytes);
+    return alloc_err == hipSuccess;
   };
   const int LT = 1 << kStageLog;
   const int64_t NSM = (int64_t)1 << fft_tile_log(pl->fp64);
@@ -787,7 +789,11 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
       !dev_alloc(&pl->d_D, 16 * (size_t)g.n_freq) ||
       !dev_alloc((void**)&pl->d_gl, sizeof(double) * n_gl)) {
     (void)hipGetLastError();
-    return cleanup_fail(fail(FCHI2_ERR_NOMEM, "plan table allocation failed"));
+    // Out of device memory is NOMEM; anything else (no device, a broken
+    // runtime) is a HIP error carrying the runtime's message.
+    if (alloc_err == hipErrorOutOfMemory)
+      return cleanup_fail(fail(FCHI2_ERR_NOMEM, "plan table allocation failed"));
+    return cleanup_fail(hip_fail(alloc_err, "plan table allocation"));
   }
   // FP64 twiddle tables: omega_{2^13}^e and omega_L^e for e < 2^tile.
   std::vector<double> hs(2 * (size_t)LT), hsm(2 * (size_t)NSM);
