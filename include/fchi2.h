@@ -104,6 +104,19 @@ typedef struct {
                                 deconvolution; reproduces the paper's
                                 sensitivity loss; no backward)                */
   int32_t curves_per_wave;   /* curves transformed together; 0 = automatic   */
+  int64_t first_bin;         /* k0 >= 0: the plan searches the band of bins
+                                f = (k0 + k) f_max / n_freq, k < n_freq (one
+                                share of a search split by frequency band
+                                over several devices).  0 = the ordinary
+                                search from f = 0.  k0 > 0 multiplies every
+                                point's strengths by exp(+2 pi i k0 m u) (u =
+                                df (t - T0), FP64 phase) and gives each
+                                harmonic grid its own complex grid of the same
+                                length (twice the FFT work of the packed
+                                real grids); such plans support fchi2_search,
+                                fchi2_search_curves and fchi2_autotune only
+                                (no backward, top-K, shared alpha, floor
+                                gridding)                                      */
 } fchi2_plan_desc_t;
 
 /*

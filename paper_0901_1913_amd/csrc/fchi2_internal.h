@@ -10,7 +10,7 @@
 namespace fchi2 {
 
 constexpr int kHMax = 8;            // harmonics supported by the register solver
-constexpr int kMaxPairs = 12;       // ceil(3 * kHMax / 2)
+constexpr int kMaxPairs = 24;       // 3 * kHMax (band plans: one grid per harmonic)
 constexpr int kMaxPasses = 4;       // FFT passes (digits of the grid length)
 constexpr int kStageLog = 13;       // stage twiddle table is omega_{2^13}
 
@@ -97,7 +97,8 @@ struct Geom {
   int H;            // harmonics
   int P;            // packed complex grids per curve
   int chunk;        // extents are rounded up to a multiple of this
-  int pad;
+  int band;         // 1: band plan (first bin k0 > 0, one complex grid per harmonic)
+  int64_t k0;       // first bin of the band (0 for the ordinary search)
   // For pair p, component j (0 = real part, 1 = imaginary part):
   // harmonic multiple m (0 = unused) and strength kind (0: w, 1: w*(x-xbar)).
   int8_t comp_m[kMaxPairs][2];

@@ -676,6 +676,13 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   if (d.kernel_width == 1 && (d.flags & FCHI2_KEEP_FOR_BACKWARD))
     return fail(FCHI2_ERR_UNSUPPORTED, "floor gridding has no backward");
   if (d.curves_per_wave < 0) return fail(FCHI2_ERR_ARG, "curves_per_wave must be >= 0");
+  if (d.first_bin < 0) return fail(FCHI2_ERR_ARG, "first_bin must be >= 0");
+  if (d.first_bin > ((int64_t)1 << 40))
+    return fail(FCHI2_ERR_UNSUPPORTED, "first_bin must be <= 2^40");
+  if (d.first_bin > 0 && (d.flags & FCHI2_KEEP_FOR_BACKWARD))
+    return fail(FCHI2_ERR_UNSUPPORTED, "band plans (first_bin > 0) have no backward");
+  if (d.first_bin > 0 && d.kernel_width == 1)
+    return fail(FCHI2_ERR_UNSUPPORTED, "band plans (first_bin > 0) have no floor gridding");
 
   fchi2_plan_s* pl = new fchi2_plan_s();
   pl->desc = d;
@@ -696,14 +703,22 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   g.beta = 2.30 * g.w;
   g.c_off = g.w == 1 ? 0 : g.w / 2 + 2;
   g.H = d.H;
-  g.P = d.H + (d.H + 1) / 2;
+  g.band = d.first_bin > 0 ? 1 : 0;
+  g.k0 = d.first_bin;
+  g.P = g.band ? 3 * d.H : d.H + (d.H + 1) / 2;
   std::memset(g.comp_m, 0, sizeof g.comp_m);
   std::memset(g.comp_kind, 0, sizeof g.comp_kind);
-  // Like is packed with like, so each FFT's rounding noise scales with the
-  // norm of grids of the same kind: pairs p < H hold the weight grids
+  // Band plans: the modulated strengths are complex, so grid p holds one
+  // harmonic, q_{p+1} for p < 2H and p_{p-2H+1} after.
+  // Otherwise like is packed with like, so each FFT's rounding noise scales
+  // with the norm of grids of the same kind: pairs p < H hold the weight grids
   // (q_{2p+1}, q_{2p+2}); pairs p >= H hold the weighted-data grids
   // (p_{2j+1}, p_{2j+2}), j = p - H, the second part empty past H.
-  for (int p = 0; p < g.P; ++p) {
+  for (int p = 0; p < g.P && g.band; ++p) {
+    g.comp_m[p][0] = (int8_t)(p < 2 * d.H ? p + 1 : p - 2 * d.H + 1);
+    g.comp_kind[p][0] = (int8_t)(p < 2 * d.H ? 0 : 1);
+  }
+  for (int p = 0; p < g.P && !g.band; ++p) {
     if (p < d.H) {
       g.comp_m[p][0] = (int8_t)(2 * p + 1);
       g.comp_m[p][1] = (int8_t)(2 * p + 2);
@@ -984,7 +999,7 @@ fchi2_status_t fchi2_top_peaks(fchi2_plan_t plan, const void* dchi2, int32_t hro
 }
 
 size_t fchi2_search_top_workspace_bytes(fchi2_plan_t plan, int32_t K) {
-  if (!plan || K < 1 || K > 64) return 0;
+  if (!plan || K < 1 || K > 64 || plan->g.band) return 0;
   return top_ws_bytes(plan, K);
 }
 
@@ -996,6 +1011,7 @@ fchi2_status_t fchi2_search_top(fchi2_plan_t plan, const double* t, const double
   if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
   if (!t || !x || !sigma || !out || !out->idx || !out->log_p)
     return fail(FCHI2_ERR_ARG, "t, x, sigma, out, out->idx and out->log_p must not be NULL");
+  if (plan->g.band) return fail(FCHI2_ERR_UNSUPPORTED, "band plans have no top-K epilogue");
   if (K < 1 || K > 64) return fail(FCHI2_ERR_ARG, "K must be in 1..64");
   if (hrow < 0 || hrow >= plan->g.H) return fail(FCHI2_ERR_ARG, "hrow must be in 0..H-1");
   if (k_lo < 0) return fail(FCHI2_ERR_ARG, "k_lo must be >= 0");
@@ -1062,7 +1078,8 @@ fchi2_status_t fchi2_fine_search(fchi2_plan_t plan, const double* t, const doubl
 }
 
 size_t fchi2_search_multi_workspace_bytes(fchi2_plan_t plan, int32_t n_sources) {
-  if (!plan || n_sources < 1 || plan->desc.n_curves != 1 || plan->g.H > 5) return 0;
+  if (!plan || n_sources < 1 || plan->desc.n_curves != 1 || plan->g.H > 5 || plan->g.band)
+    return 0;
   return multi_layout(plan, n_sources).bytes;
 }
 
@@ -1077,6 +1094,7 @@ fchi2_status_t fchi2_search_multi(fchi2_plan_t plan, const double* t, const doub
   if (plan->desc.n_curves != 1)
     return fail(FCHI2_ERR_ARG, "the shared time base needs a plan of one curve");
   if (plan->g.H > 5) return fail(FCHI2_ERR_UNSUPPORTED, "shared-alpha search supports H <= 5");
+  if (plan->g.band) return fail(FCHI2_ERR_UNSUPPORTED, "band plans have no shared-alpha search");
   if (n_sources < 1) return fail(FCHI2_ERR_ARG, "n_sources must be >= 1");
   if (!workspace) return fail(FCHI2_ERR_ARG, "workspace is NULL");
   if (((uintptr_t)workspace & 255) != 0)
@@ -1100,6 +1118,7 @@ fchi2_status_t fchi2_autotune_multi(fchi2_plan_t plan, const double* t, const do
   if (plan->desc.n_curves != 1)
     return fail(FCHI2_ERR_ARG, "the shared time base needs a plan of one curve");
   if (plan->g.H > 5) return fail(FCHI2_ERR_UNSUPPORTED, "shared-alpha search supports H <= 5");
+  if (plan->g.band) return fail(FCHI2_ERR_UNSUPPORTED, "band plans have no shared-alpha search");
   if (n_sources < 1) return fail(FCHI2_ERR_ARG, "n_sources must be >= 1");
   if (!workspace || ((uintptr_t)workspace & 255) != 0)
     return fail(FCHI2_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");

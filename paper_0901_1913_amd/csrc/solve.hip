@@ -1,6 +1,7 @@
 // Per-frequency Delta chi2 for every H' = 1..H: one thread per bin runs the
 // shared per-bin solve and writes all H rows and the bin's flags.
 #include <cmath>
+#include <type_traits>
 
 #include "fchi2_internal.h"
 #include "launch.h"
@@ -14,7 +15,7 @@ constexpr int kNT = 256;
 
 using namespace solve_detail;
 
-template <int H, typename R, typename O>
+template <int H, typename R, typename O, bool BAND>
 __global__ __launch_bounds__(kNT) void k_solve(const cplx<R>* __restrict__ zc,
                                                const cplx<double>* __restrict__ D,
                                                const Moments* __restrict__ mom, Geom g,
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(kNT) void k_solve(const cplx<R>* __restrict__ zc,
   if (k >= nf) return;
   const Moments mo = mom[c];
   O d[H];
-  const uint8_t fl = solve_bin<H, R, O>(zc, D, mo, g, cw, k, eps, d);
+  const uint8_t fl = solve_bin<H, R, O, BAND>(zc, D, mo, g, cw, k, eps, d);
   O* o = out + (int64_t)c * H * nf + k;
 #pragma unroll
   for (int h = 0; h < H; ++h) o[h * nf] = d[h];
@@ -39,13 +40,21 @@ hipError_t solve_h(bool fp64, const void* zc, const void* D, const Moments* mom,
                    int curve0, int n_curves, double eps, void* out, uint8_t* flags,
                    hipStream_t st) {
   dim3 gr((unsigned)((g.n_freq + kNT - 1) / kNT), (unsigned)n_curves);
-  if (fp64)
-    hipLaunchKernelGGL((k_solve<H, double, double>), gr, dim3(kNT), 0, st,
-                       (const cplx<double>*)zc, (const cplx<double>*)D, mom, g, curve0, eps,
-                       (double*)out, flags);
+  auto launch = [&](auto band) {
+    constexpr bool B = decltype(band)::value;
+    if (fp64)
+      hipLaunchKernelGGL((k_solve<H, double, double, B>), gr, dim3(kNT), 0, st,
+                         (const cplx<double>*)zc, (const cplx<double>*)D, mom, g, curve0, eps,
+                         (double*)out, flags);
+    else
+      hipLaunchKernelGGL((k_solve<H, float, float, B>), gr, dim3(kNT), 0, st,
+                         (const cplx<float>*)zc, (const cplx<double>*)D, mom, g, curve0, eps,
+                         (float*)out, flags);
+  };
+  if (g.band)
+    launch(std::true_type{});
   else
-    hipLaunchKernelGGL((k_solve<H, float, float>), gr, dim3(kNT), 0, st, (const cplx<float>*)zc,
-                       (const cplx<double>*)D, mom, g, curve0, eps, (float*)out, flags);
+    launch(std::false_type{});
   return hipGetLastError();
 }
 

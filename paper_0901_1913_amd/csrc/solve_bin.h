@@ -71,6 +71,33 @@ __device__ __forceinline__ void load_spectra(const cplx<R>* __restrict__ zc, int
   }
 }
 
+// Band plans: grid p holds one harmonic with complex (modulated) strengths,
+// q_{p+1} for p < 2H and p_{p-2H+1} after, so Q_m and P_m are the grid
+// spectra at bin k directly, times D[k].
+template <int H, typename R>
+__device__ __forceinline__ void load_band(const cplx<R>* __restrict__ zc, int64_t nf,
+                                          int64_t base_grid, int64_t k, cplx<double> Dk_,
+                                          double W, double* Qr, double* Qi, double* Pr,
+                                          double* Pi) {
+  const double Dr = (double)Dk_.x, Di = (double)Dk_.y;
+  Qr[0] = W;
+  Qi[0] = 0.0;
+  Pr[0] = 0.0;
+  Pi[0] = 0.0;
+#pragma unroll
+  for (int m = 1; m <= 2 * H; ++m) {
+    const cplx<R> z = zc[((base_grid + m - 1) * 2) * nf + k];
+    Qr[m] = (double)z.x * Dr - (double)z.y * Di;
+    Qi[m] = (double)z.x * Di + (double)z.y * Dr;
+  }
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    const cplx<R> z = zc[((base_grid + 2 * H + m - 1) * 2) * nf + k];
+    Pr[m] = (double)z.x * Dr - (double)z.y * Di;
+    Pi[m] = (double)z.x * Di + (double)z.y * Dr;
+  }
+}
+
 __device__ __forceinline__ double Cp(const double* Qr, int gdiff) {
   return Qr[gdiff < 0 ? -gdiff : gdiff];
 }
@@ -258,8 +285,9 @@ __device__ __forceinline__ void load_p(const cplx<R>* __restrict__ zc, int64_t n
 
 // Delta chi2 of bin k of curve c (wave slot cw) for H' = 1..H, rounded to the
 // output type, into d[0..H-1]; returns the bin's flags.  Curves with a fatal
-// data flag give NaN rows; k = 0 gives zero rows and the DC flag.
-template <int H, typename R, typename O>
+// data flag give NaN rows; bin 0 gives zero rows and the DC flag.  BAND: a
+// band plan's grids (bin k is bin k0 + k of the search).
+template <int H, typename R, typename O, bool BAND = false>
 __device__ __forceinline__ uint8_t solve_bin(const cplx<R>* __restrict__ zc,
                                              const cplx<double>* __restrict__ D,
                                              const Moments& mo, const Geom& g, int cw, int64_t k,
@@ -272,15 +300,19 @@ __device__ __forceinline__ uint8_t solve_bin(const cplx<R>* __restrict__ zc,
     return (uint8_t)(mo.flags & 0xF8u);
   }
   uint8_t fl = 0;
-  const double f = (double)k * g.df;
+  const int64_t kg = BAND ? g.k0 + k : k;  // bin of the search
+  const double f = (double)kg * g.df;
   if (mo.span > 0.0 && f * mo.span < 1.0) fl |= BF_LOW_F;
-  if (k == 0) {
+  if (kg == 0) {
 #pragma unroll
     for (int h = 0; h < H; ++h) d[h] = (O)0;
     return (uint8_t)(fl | BF_DC);
   }
   double Qr[2 * H + 1], Qi[2 * H + 1], Pr[H + 1], Pi[H + 1];
-  load_spectra<H, R>(zc, g.n_freq, (int64_t)cw * P, k, D[k], mo.W, Qr, Qi, Pr, Pi);
+  if constexpr (BAND)
+    load_band<H, R>(zc, g.n_freq, (int64_t)cw * g.P, k, D[k], mo.W, Qr, Qi, Pr, Pi);
+  else
+    load_spectra<H, R>(zc, g.n_freq, (int64_t)cw * P, k, D[k], mo.W, Qr, Qi, Pr, Pi);
   double Lm[dd][dd];
   double inv[dd];
   double z[dd];

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kNT) void k_tile_bounds(const double* __restrict__ 
   for (int64_t q = t_min; q <= t_max; ++q) row[q] = (int32_t)il;
 }
 
-template <typename S, int LOGB>
+template <typename S, int LOGB, bool BAND>
 __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ sigma,
@@ -335,7 +335,22 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
         const double wy = w * (x[i + mo.xshift] - mo.xbar);
         const double sa = (kind_a == 0) ? w : wy;
         double sre, sim;
-        if (comp == 0) {
+        if constexpr (BAND) {
+          // Band plan: strength times exp(+2 pi i k0 m u), so that bin k of
+          // the grid is bin k0 + k of the search.  The phase k0 m u in
+          // cycles is reduced modulo 1 from the FP64 product and its exact
+          // rounding residual.
+          const double km = (double)(g.k0 * (int64_t)m);
+          const double u = (t[i] - mo.T0) * g.df;
+          const double ph = km * u;
+          const double r = fma(km, u, -ph);
+          double fr = (ph - floor(ph)) + r;
+          fr -= floor(fr);
+          double sn, cs;
+          sincospi(2.0 * fr, &sn, &cs);
+          sre = sa * cs;
+          sim = sa * sn;
+        } else if (comp == 0) {
           sre = sa;
           sim = both ? ((kind_b == 0) ? w : wy) : 0.0;
         } else {
@@ -445,14 +460,21 @@ hipError_t launch_spread(bool fp64, const double* t, const double* x, const doub
   // Blocks stride over the non-empty tiles of each curve (counted on the device).
   const int64_t cap = std::max<int64_t>(8, 4096 / std::max(n_curves, 1));
   dim3 gr((unsigned)std::min<int64_t>(cap, tiles * g.P), 1u, (unsigned)n_curves);
-  auto launch = [&](auto logb) -> void {
+  auto launch_b = [&](auto logb, auto band) -> void {
     constexpr int LB = decltype(logb)::value;
+    constexpr bool BD = decltype(band)::value;
     if (fp64)
-      hipLaunchKernelGGL((k_spread<double, LB>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
+      hipLaunchKernelGGL((k_spread<double, LB, BD>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
                          curve0, tb, ntb, share_tb ? 1 : 0, (cplx<double>*)grid);
     else
-      hipLaunchKernelGGL((k_spread<float, LB>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
+      hipLaunchKernelGGL((k_spread<float, LB, BD>), gr, dim3(kNT), 0, st, t, x, sigma, mom, g,
                          curve0, tb, ntb, share_tb ? 1 : 0, (cplx<float>*)grid);
+  };
+  auto launch = [&](auto logb) -> void {
+    if (g.band)
+      launch_b(logb, std::true_type{});
+    else
+      launch_b(logb, std::false_type{});
   };
   switch (log_tile) {
     case 10: launch(std::integral_constant<int, 10>{}); break;

@@ -51,6 +51,7 @@ class PlanDesc(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("kernel_width", ctypes.c_int32),
         ("curves_per_wave", ctypes.c_int32),
+        ("first_bin", ctypes.c_int64),
     ]
 
 
@@ -180,12 +181,16 @@ def _dev_ptr(tensor, dtype, n=None, name="tensor"):
 
 
 class Plan:
-    """A search plan: geometry, FFT split and device tables for a set of curves."""
+    """A search plan: geometry, FFT split and device tables for a set of curves.
+
+    first_bin = k0 > 0 makes a band plan: its rows hold bins k0 .. k0 + n_freq - 1
+    of the search with bin spacing f_max / n_freq (one share of a search split by
+    frequency band); such plans support search, search_curves and autotune."""
 
     def __init__(self, offsets: Sequence[int], f_max: float, H: int, n_freq: int,
                  precision: str = "mixed", keep_for_backward: bool = False,
                  graph: bool = False, kernel_width: int = 0, curves_per_wave: int = 0,
-                 stream=None):
+                 first_bin: int = 0, stream=None):
         torch = _torch()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         if off.ndim != 1 or off.shape[0] < 2:
@@ -199,7 +204,7 @@ class Plan:
             offsets=off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
             f_max=float(f_max), H=int(H), n_freq=int(n_freq),
             precision=FP64 if precision == "fp64" else MIXED,
-            flags=flags, kernel_width=int(kernel_width),
+            flags=flags, kernel_width=int(kernel_width), first_bin=int(first_bin),
             curves_per_wave=int(curves_per_wave))
         handle = ctypes.c_void_p()
         st = _stream_handle(stream) if torch.cuda.is_available() else 0
@@ -209,6 +214,7 @@ class Plan:
         self.n_total = int(off[-1])
         self.H, self.n_freq, self.f_max = int(H), int(n_freq), float(f_max)
         self.precision = precision
+        self.first_bin = int(first_bin)
         self.keep_for_backward = keep_for_backward
         self.out_dtype = torch.float64 if precision == "fp64" else torch.float32
         self.workspace_bytes = int(lib().fchi2_workspace_bytes(self._h))
@@ -301,6 +307,8 @@ class Plan:
         }
         need = int(lib().fchi2_search_top_workspace_bytes(self._h, int(K)))
         if need == 0:
+            if self.first_bin > 0:
+                raise FChi2Error(ERR_UNSUPPORTED, "band plans have no top-K epilogue")
             raise FChi2Error(ERR_ARG, "K must be in 1..64")
         ws = self.workspace(dev, need) if workspace is None else workspace
         out = TopOut(*(ctypes.c_void_p(res[k].data_ptr()) for k in

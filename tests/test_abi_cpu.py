@@ -59,6 +59,10 @@ def _plan(**kw):
     (dict(offsets=[1, 5]), F.ERR_ARG, "offsets[0]"),
     (dict(offsets=[0, 5, 3]), F.ERR_ARG, "nondecreasing"),
     (dict(curves_per_wave=-1), F.ERR_ARG, "curves_per_wave"),
+    (dict(first_bin=-1), F.ERR_ARG, "first_bin"),
+    (dict(first_bin=2 ** 41), F.ERR_UNSUPPORTED, "first_bin"),
+    (dict(first_bin=4096, flags=F.KEEP_FOR_BACKWARD), F.ERR_UNSUPPORTED, "no backward"),
+    (dict(first_bin=4096, kernel_width=1), F.ERR_UNSUPPORTED, "no floor gridding"),
 ])
 def test_plan_argument_errors(kw, code, frag):
     st, msg = _plan(**kw)

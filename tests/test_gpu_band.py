@@ -1,0 +1,84 @@
+"""Band plans (first_bin = k0 > 0): rows hold bins k0 .. k0 + n_freq - 1 of the
+search at the ordinary bin spacing, the share one device computes when a
+search is split by frequency band.  Checked against the FP64 oracle at those
+frequencies (gate and tolerance as in the other parity tests: relative error
+on max(Delta chi2, 2H') <= 1e-5 mixed, 1e-8 FP64) and against the ordinary
+search over the whole range at the same bins.
+"""
+import numpy as np
+import pytest
+
+from oracle import fchi2_oracle as ora
+from paper_0901_1913_amd import fchi2 as F
+from paper_0901_1913_amd import synth
+from tests.gpu_util import note, run_search, sample_bins, to_dev
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = {"mixed": 1e2, "fp64": 1e6}
+TOL = {"mixed": 1e-5, "fp64": 1e-8}
+G = 4  # bands of the whole range
+
+
+def _band_search(full, precision, g, tune=False):
+    import torch
+    nb = full.n_freq // G
+    plan = F.Plan(full.offsets, full.f_max / G, full.H, nb, precision=precision,
+                  first_bin=g * nb)
+    t, x, s = to_dev(full)
+    if tune:
+        print(f"[gpu] band autotuned: {plan.autotune(t, x, s)}", flush=True)
+    d, c0, fl = plan.search(t, x, s)
+    torch.cuda.synchronize()
+    return d.double().cpu().numpy(), c0.cpu().numpy(), fl.cpu().numpy(), plan
+
+
+@pytest.mark.parametrize("precision,g", [("fp64", 3), ("mixed", 1), ("mixed", 3)])
+def test_band_matches_oracle_and_the_full_search(precision, g):
+    # df = 10 / 2^14; 2H df span = 0.37 < 1 (no wrap)
+    full = synth.make("plain", n=400, n_freq=2 ** 14, f_max=10.0)
+    nb = full.n_freq // G
+    k0 = g * nb
+    note(f"band {g} of {G}, {precision}, k0 = {k0}, n_freq = {nb}")
+    d_b, c0_b, fl_b, _ = _band_search(full, precision, g, tune=(precision == "mixed"))
+    note(f"full range, {precision}")
+    d_f, c0_f, fl_f, _ = run_search(full, precision)
+    np.testing.assert_allclose(c0_b, c0_f, rtol=1e-12)
+
+    # oracle at the band's frequencies
+    t, x, s = full.curve(0)
+    kk = sample_bins(nb, 400, 31 + g, k_min=0)
+    freqs = (k0 + kk) * (full.f_max / full.n_freq)
+    res = ora.dchi2(t, x, s, freqs, full.H)
+    err = ora.rel_err(d_b[0][:, kk], res["dchi2"])
+    gate = ora.gate_mask(res, freqs, KAPPA[precision])
+    assert gate.sum() > 0.9 * len(kk)
+    e = err[:, gate]
+    print(f"band vs oracle: gated {gate.sum()}/{len(kk)} max {e.max():.3e} "
+          f"median {np.median(e):.3e}", flush=True)
+    assert e.max() <= TOL[precision]
+
+    # the same bins of the ordinary search over the whole range
+    sub = d_f[0][:, k0:k0 + nb]
+    floor = 2.0 * np.arange(1, full.H + 1)[:, None]
+    rel = np.abs(d_b[0] - sub) / np.maximum(np.abs(sub), floor)
+    ok = ((fl_b[0] | fl_f[0, k0:k0 + nb]) & F.BIN_PIVOT) == 0
+    r = rel[:, ok]
+    print(f"band vs full search: {ok.sum()} bins, median {np.median(r):.3e} "
+          f"p99.9 {np.quantile(r, 0.999):.3e} max {r.max():.3e}", flush=True)
+    assert np.quantile(r, 0.999) <= TOL[precision]
+    assert np.median(r) <= 0.1 * TOL[precision]
+    # bin flags that depend only on the frequency agree; no DC bin in a band
+    mask = F.BIN_LOW_F | F.BIN_DC
+    assert np.array_equal(fl_b[0] & mask, fl_f[0, k0:k0 + nb] & mask)
+    assert not np.any(fl_b[0] & F.BIN_DC)
+
+
+def test_band_plan_refuses_what_it_does_not_support():
+    full = synth.make("plain", n=400, n_freq=2 ** 14, f_max=10.0)
+    note("band plan: top-K refused")
+    _, _, _, plan = _band_search(full, "mixed", 2)
+    t, x, s = to_dev(full)
+    with pytest.raises(F.FChi2Error) as e:
+        plan.search_top(t, x, s, K=4)
+    assert e.value.status == F.ERR_UNSUPPORTED
