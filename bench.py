@@ -345,6 +345,44 @@ def variants_timing(steps):
             "unit": "freq*H/s"}
 
 
+def band_share_timing(steps, G=8):
+    """One device's share of the stress curve split into G frequency bands
+    (same bin spacing, n_freq / G bins): the first band is an ordinary plan,
+    any other band a band plan (first_bin > 0, modulated complex grids)."""
+    import torch
+    from paper_0901_1913_amd import fchi2 as F
+    from paper_0901_1913_amd import synth
+    cur = synth.make("stress")
+    nb = cur.n_freq // G
+    t = torch.from_numpy(cur.t).cuda()
+    x = torch.from_numpy(cur.x).cuda()
+    s = torch.from_numpy(cur.sigma).cuda()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    out = {"workload": "stress", "n": int(cur.t.shape[0]), "H": cur.H, "bands": G,
+           "n_freq_per_band": nb, "precision": "mixed", "unit": "freq*H/s"}
+    for g in (0, 1):
+        plan = F.Plan(cur.offsets, cur.f_max / G, cur.H, nb, precision="mixed",
+                      first_bin=g * nb)
+        schedule = plan.autotune(t, x, s)
+        d, c0, fl = plan.search(t, x, s)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.search(t, x, s, dchi2=d, chi2_0=c0, flags=fl)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        plan.close()
+        del d, c0, fl
+        out[f"band{g}_ms"] = round(ms, 4)
+        out[f"band{g}_value"] = round(nb * cur.H / (ms * 1e-3), 1)
+        out[f"band{g}_schedule"] = schedule
+        log(f"stress band {g} of {G}: {ms:.3f} ms")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,6 +401,8 @@ def main(argv=None):
                     help="skip the floor-gridding and detrending timings")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the adjoint timing on the diff workload")
+    ap.add_argument("--no-band", action="store_true",
+                    help="skip the frequency-band share of the stress curve")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device copy of this many MiB (a known-size kernel "
                          "against which HBM counters are scaled)")
@@ -530,6 +570,8 @@ def main(argv=None):
         out["gradient"] = gradient_timing(a.steps)
     if not a.no_variants:
         out["variants"] = variants_timing(a.steps)
+    if not a.no_band:
+        out["band_share"] = band_share_timing(a.steps)
     print(json.dumps(out), flush=True)
     return 0
 

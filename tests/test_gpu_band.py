@@ -82,3 +82,34 @@ def test_band_plan_refuses_what_it_does_not_support():
     with pytest.raises(F.FChi2Error) as e:
         plan.search_top(t, x, s, K=4)
     assert e.value.status == F.ERR_UNSUPPORTED
+
+
+def test_stress_band_share_full_shape():
+    """One device's share of the stress curve split into 8 bands, at its real
+    shape (n = 1e6, H = 8, 2^21 bins, mixed, autotuned): band 1, which holds
+    the injected period 0.1234 d."""
+    cur = synth.make("stress")
+    G8, g = 8, 1
+    nb = cur.n_freq // G8
+    k0 = g * nb
+    note(f"stress band {g} of {G8}: k0 = {k0}, n_freq = {nb}, mixed")
+    import torch
+    plan = F.Plan(cur.offsets, cur.f_max / G8, cur.H, nb, precision="mixed", first_bin=k0)
+    t, x, s = to_dev(cur)
+    print(f"[gpu] autotuned: {plan.autotune(t, x, s)}", flush=True)
+    d, _, fl = plan.search(t, x, s)
+    torch.cuda.synchronize()
+    d = d.double().cpu().numpy()[0]
+    kp = int(round(cur.n_freq / cur.f_max / 0.1234)) - k0  # injected peak, band-relative
+    assert 0 < kp < nb
+    kk = np.unique(np.concatenate([sample_bins(nb, 16, 57, k_min=0), [kp - 1, kp, kp + 1]]))
+    tt, xx, ss = cur.curve(0)
+    freqs = (k0 + kk) * (cur.f_max / cur.n_freq)
+    res = ora.dchi2(tt, xx, ss, freqs, cur.H)
+    err = ora.rel_err(d[:, kk], res["dchi2"])
+    gate = ora.gate_mask(res, freqs, KAPPA["mixed"])
+    e = err[:, gate]
+    print(f"stress band vs oracle: gated {gate.sum()}/{len(kk)} max {e.max():.3e} "
+          f"median {np.median(e):.3e}", flush=True)
+    assert gate.sum() >= len(kk) - 2 and e.max() <= TOL["mixed"]
+    assert abs(int(np.argmax(d[cur.H - 1])) - kp) <= 1
