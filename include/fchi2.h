@@ -109,11 +109,14 @@ typedef struct {
                                 share of a search split by frequency band
                                 over several devices).  0 = the ordinary
                                 search from f = 0.  k0 > 0 multiplies every
-                                point's strengths by exp(+2 pi i k0 m u) (u =
+                                point's strengths by exp(+2 pi i kc m u) (kc =
+                                k0 + n_freq/2 the band's middle bin, u =
                                 df (t - T0), FP64 phase) and gives each
-                                harmonic grid its own complex grid of the same
-                                length (twice the FFT work of the packed
-                                real grids); such plans support fchi2_search,
+                                harmonic its own complex grid of 2 n_freq
+                                cells centred on the band (as many grid
+                                elements as the packed real grids of the
+                                ordinary search; n_freq >= 2^11); such plans
+                                support fchi2_search,
                                 fchi2_search_curves and fchi2_autotune only
                                 (no backward, top-K, shared alpha, floor
                                 gridding)                                      */

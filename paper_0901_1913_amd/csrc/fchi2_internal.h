@@ -87,7 +87,7 @@ __host__ __device__ inline cplx<R> cmul(cplx<R> a, cplx<R> b) {
 
 // Grid geometry and spreading kernel shared by spread, FFT, solve and gather.
 struct Geom {
-  int64_t L;        // complex grid length (cells) = 4 * n_freq
+  int64_t L;        // complex grid length (cells): 4 n_freq (2 n_freq in a band plan)
   int64_t n_freq;   // trial bins per curve
   double df;        // bin spacing (cycles per unit time)
   double beta;      // exponential-of-semicircle kernel shape
@@ -97,7 +97,8 @@ struct Geom {
   int H;            // harmonics
   int P;            // packed complex grids per curve
   int chunk;        // extents are rounded up to a multiple of this
-  int band;         // 1: band plan (first bin k0 > 0, one complex grid per harmonic)
+  int band;         // 1: band plan (first bin k0 > 0, one complex grid per harmonic,
+                    //    centred on bin k0 + n_freq / 2)
   int64_t k0;       // first bin of the band (0 for the ordinary search)
   // For pair p, component j (0 = real part, 1 = imaginary part):
   // harmonic multiple m (0 = unused) and strength kind (0: w, 1: w*(x-xbar)).

@@ -696,7 +696,11 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
 
   Geom& g = pl->g;
   g.n_freq = d.n_freq;
-  g.L = 4 * d.n_freq;
+  // Real grids of 4 n_freq cells keep bins k < n_freq (upsampling 2 over
+  // [-n_freq, n_freq)); a band plan's complex grids are centred on the band,
+  // whose offsets [-n_freq/2, n_freq/2) need 2 n_freq cells for the same
+  // upsampling.
+  g.L = (d.first_bin > 0 ? 2 : 4) * d.n_freq;
   g.df = d.f_max / (double)d.n_freq;
   g.w = d.kernel_width ? d.kernel_width : (pl->fp64 ? 14 : 10);
   g.half_w = 0.5 * g.w;

@@ -72,27 +72,35 @@ __device__ __forceinline__ void load_spectra(const cplx<R>* __restrict__ zc, int
 }
 
 // Band plans: grid p holds one harmonic with complex (modulated) strengths,
-// q_{p+1} for p < 2H and p_{p-2H+1} after, so Q_m and P_m are the grid
-// spectra at bin k directly, times D[k].
+// q_{p+1} for p < 2H and p_{p-2H+1} after, centred on the band's middle bin:
+// band bin k is offset o = k - n_freq/2 from the centre, read from the direct
+// half at o >= 0 (grid bin o) and from the mirror half at -o otherwise (grid
+// bin L + o), times the deconvolution factor of o (D[-o] conjugated: the
+// kernel transform is even and the origin-shift phase odd in o).
 template <int H, typename R>
-__device__ __forceinline__ void load_band(const cplx<R>* __restrict__ zc, int64_t nf,
-                                          int64_t base_grid, int64_t k, cplx<double> Dk_,
-                                          double W, double* Qr, double* Qi, double* Pr,
-                                          double* Pi) {
-  const double Dr = (double)Dk_.x, Di = (double)Dk_.y;
+__device__ __forceinline__ void load_band(const cplx<R>* __restrict__ zc,
+                                          const cplx<double>* __restrict__ D, int64_t nf,
+                                          int64_t base_grid, int64_t k, double W, double* Qr,
+                                          double* Qi, double* Pr, double* Pi) {
+  const int64_t o = k - nf / 2;
+  const bool neg = o < 0;
+  const int64_t j = neg ? -o : o;
+  const int64_t half = neg ? 1 : 0;
+  const cplx<double> Dj = D[j];
+  const double Dr = Dj.x, Di = neg ? -Dj.y : Dj.y;
   Qr[0] = W;
   Qi[0] = 0.0;
   Pr[0] = 0.0;
   Pi[0] = 0.0;
 #pragma unroll
   for (int m = 1; m <= 2 * H; ++m) {
-    const cplx<R> z = zc[((base_grid + m - 1) * 2) * nf + k];
+    const cplx<R> z = zc[((base_grid + m - 1) * 2 + half) * nf + j];
     Qr[m] = (double)z.x * Dr - (double)z.y * Di;
     Qi[m] = (double)z.x * Di + (double)z.y * Dr;
   }
 #pragma unroll
   for (int m = 1; m <= H; ++m) {
-    const cplx<R> z = zc[((base_grid + 2 * H + m - 1) * 2) * nf + k];
+    const cplx<R> z = zc[((base_grid + 2 * H + m - 1) * 2 + half) * nf + j];
     Pr[m] = (double)z.x * Dr - (double)z.y * Di;
     Pi[m] = (double)z.x * Di + (double)z.y * Dr;
   }
@@ -310,7 +318,7 @@ __device__ __forceinline__ uint8_t solve_bin(const cplx<R>* __restrict__ zc,
   }
   double Qr[2 * H + 1], Qi[2 * H + 1], Pr[H + 1], Pi[H + 1];
   if constexpr (BAND)
-    load_band<H, R>(zc, g.n_freq, (int64_t)cw * g.P, k, D[k], mo.W, Qr, Qi, Pr, Pi);
+    load_band<H, R>(zc, D, g.n_freq, (int64_t)cw * g.P, k, mo.W, Qr, Qi, Pr, Pi);
   else
     load_spectra<H, R>(zc, g.n_freq, (int64_t)cw * P, k, D[k], mo.W, Qr, Qi, Pr, Pi);
   double Lm[dd][dd];

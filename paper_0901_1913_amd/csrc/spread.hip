@@ -336,11 +336,12 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
         const double sa = (kind_a == 0) ? w : wy;
         double sre, sim;
         if constexpr (BAND) {
-          // Band plan: strength times exp(+2 pi i k0 m u), so that bin k of
-          // the grid is bin k0 + k of the search.  The phase k0 m u in
-          // cycles is reduced modulo 1 from the FP64 product and its exact
-          // rounding residual.
-          const double km = (double)(g.k0 * (int64_t)m);
+          // Band plan: strength times exp(+2 pi i kc m u), kc = k0 + n_freq/2
+          // the band's middle bin, so that grid bin j (j - L for j >= L/2)
+          // is bin kc + j of the search.  The phase kc m u in cycles is
+          // reduced modulo 1 from the FP64 product and its exact rounding
+          // residual.
+          const double km = (double)((g.k0 + g.n_freq / 2) * (int64_t)m);
           const double u = (t[i] - mo.T0) * g.df;
           const double ph = km * u;
           const double r = fma(km, u, -ph);
