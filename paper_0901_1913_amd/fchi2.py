@@ -346,7 +346,8 @@ class Plan:
         S = int(x.shape[0])
         nbytes = int(lib().fchi2_search_multi_workspace_bytes(self._h, S))
         if nbytes == 0:
-            raise FChi2Error(ERR_UNSUPPORTED, "shared-alpha search needs H <= 5")
+            raise FChi2Error(ERR_UNSUPPORTED, "shared-alpha search needs a plan of one curve, "
+                             "H <= 5 and no band (first_bin = 0)")
         ws = torch.empty(nbytes, dtype=torch.uint8, device=t.device)
         scratch = torch.empty((S, self.H, self.n_freq), dtype=self.out_dtype, device=t.device)
         _check(lib().fchi2_autotune_multi(
@@ -374,7 +375,8 @@ class Plan:
         dev = t.device
         nbytes = int(lib().fchi2_search_multi_workspace_bytes(self._h, S))
         if nbytes == 0:
-            raise FChi2Error(ERR_UNSUPPORTED, "shared-alpha search needs H <= 5")
+            raise FChi2Error(ERR_UNSUPPORTED, "shared-alpha search needs a plan of one curve, "
+                             "H <= 5 and no band (first_bin = 0)")
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         dchi2 = torch.empty((S, self.H, self.n_freq), dtype=self.out_dtype, device=dev)
         chi2_0 = torch.empty(S, dtype=f64, device=dev)

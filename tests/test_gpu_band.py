@@ -82,6 +82,11 @@ def test_band_plan_refuses_what_it_does_not_support():
     with pytest.raises(F.FChi2Error) as e:
         plan.search_top(t, x, s, K=4)
     assert e.value.status == F.ERR_UNSUPPORTED
+    import torch
+    with pytest.raises(F.FChi2Error) as e:
+        plan.search_multi(t, s, x.reshape(1, -1).contiguous(),
+                          torch.ones(1, dtype=torch.float64, device=t.device))
+    assert e.value.status == F.ERR_UNSUPPORTED
 
 
 def test_stress_band_share_full_shape():
