@@ -124,8 +124,8 @@ typedef struct {
 
 /*
  * Create a plan.  Validates `desc`, derives the grid geometry (grid length
- * L = 4 n_freq cells per harmonic grid, Section 3b's zero-padded arrays that
- * cover at least 2H times the observed span), the FFT pass split and the
+ * L = 4 n_freq cells per harmonic grid, 2 n_freq in a band plan; Section 3b's
+ * zero-padded arrays that cover at least 2H times the observed span), the FFT pass split and the
  * spreading kernel, and builds its device tables (twiddles, deconvolution) on
  * `stream`, waiting for them.  Allocates device memory for those tables
  * (owned by the plan).  On success *out receives the plan.
