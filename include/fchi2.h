@@ -116,10 +116,12 @@ typedef struct {
                                 cells centred on the band (as many grid
                                 elements as the packed real grids of the
                                 ordinary search; n_freq >= 2^11); such plans
-                                support fchi2_search,
-                                fchi2_search_curves and fchi2_autotune only
-                                (no backward, top-K, shared alpha, floor
-                                gridding)                                      */
+                                support fchi2_search, fchi2_search_curves,
+                                fchi2_autotune and fchi2_search_top (ln p
+                                with the bin index k0 + k of the search; idx,
+                                chi2_best and dchi2_adj per band; a band's
+                                first and last bins are never candidates), not
+                                backward, shared alpha or floor gridding      */
 } fchi2_plan_desc_t;
 
 /*

@@ -1003,7 +1003,7 @@ fchi2_status_t fchi2_top_peaks(fchi2_plan_t plan, const void* dchi2, int32_t hro
 }
 
 size_t fchi2_search_top_workspace_bytes(fchi2_plan_t plan, int32_t K) {
-  if (!plan || K < 1 || K > 64 || plan->g.band) return 0;
+  if (!plan || K < 1 || K > 64) return 0;
   return top_ws_bytes(plan, K);
 }
 
@@ -1015,7 +1015,6 @@ fchi2_status_t fchi2_search_top(fchi2_plan_t plan, const double* t, const double
   if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
   if (!t || !x || !sigma || !out || !out->idx || !out->log_p)
     return fail(FCHI2_ERR_ARG, "t, x, sigma, out, out->idx and out->log_p must not be NULL");
-  if (plan->g.band) return fail(FCHI2_ERR_UNSUPPORTED, "band plans have no top-K epilogue");
   if (K < 1 || K > 64) return fail(FCHI2_ERR_ARG, "K must be in 1..64");
   if (hrow < 0 || hrow >= plan->g.H) return fail(FCHI2_ERR_ARG, "hrow must be in 0..H-1");
   if (k_lo < 0) return fail(FCHI2_ERR_ARG, "k_lo must be >= 0");

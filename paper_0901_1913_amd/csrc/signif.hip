@@ -33,6 +33,7 @@
 // thread, the same wave tournaments and rank merge), and the group lists once
 // more per curve, which gives the final K.
 #include <cmath>
+#include <type_traits>
 #include <cstdint>
 
 #include "fchi2_internal.h"
@@ -69,7 +70,7 @@ __device__ __forceinline__ bool key_less(double sa, int ia, double sb, int ib) {
   return (sa < sb) || (sa == sb && ia < ib);
 }
 
-template <int H, typename R, typename O>
+template <int H, typename R, typename O, bool BAND>
 __global__ __launch_bounds__(kNT) void k_solve_top(
     const cplx<R>* __restrict__ zc, const cplx<double>* __restrict__ D,
     const Moments* __restrict__ mom, Geom g, int curve0, double eps, int hrow, int64_t k_lo,
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
     const int64_t k = B0 - 1 + i;
     if (k >= 0 && k < nf) {
       O d[H];
-      const uint8_t fl = solve_bin<H, R, O>(zc, D, mo, g, cw, k, eps, d);
+      const uint8_t fl = solve_bin<H, R, O, BAND>(zc, D, mo, g, cw, k, eps, d);
 #pragma unroll
       for (int h = 0; h < H; ++h) s_d[h][i] = d[h];
       s_fl[i] = fl;
@@ -143,7 +144,9 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
   __syncthreads();
   for (int j = lane; j < ncand; j += 64) {
     const int i = c_slot[wv][j];
-    s_sc[i] = log((double)(B0 - 1 + i)) + log_q_even((double)s_d[hrow][i], hp);
+    // ln of the bin index of the search (a band plan's rows start at k0)
+    const int64_t kg = (BAND ? g.k0 : 0) + B0 - 1 + i;
+    s_sc[i] = log((double)kg) + log_q_even((double)s_d[hrow][i], hp);
   }
   __syncthreads();
   double ks[kBPT];
@@ -429,14 +432,21 @@ hipError_t solve_top_h(bool fp64, const void* zc, const void* D, const Moments* 
                        const Geom& g, int curve0, int n_curves, double eps, int hrow,
                        int64_t k_lo, int K, int nblk, const TopScratch& sc, hipStream_t st) {
   dim3 gr((unsigned)nblk, (unsigned)n_curves);
-  if (fp64)
-    hipLaunchKernelGGL((k_solve_top<H, double, double>), gr, dim3(kNT), 0, st,
-                       (const cplx<double>*)zc, (const cplx<double>*)D, mom, g, curve0, eps, hrow,
-                       k_lo, K, nblk, sc.score, sc.k, sc.flag, sc.d, sc.bmax);
+  auto launch = [&](auto band) {
+    constexpr bool B = decltype(band)::value;
+    if (fp64)
+      hipLaunchKernelGGL((k_solve_top<H, double, double, B>), gr, dim3(kNT), 0, st,
+                         (const cplx<double>*)zc, (const cplx<double>*)D, mom, g, curve0, eps,
+                         hrow, k_lo, K, nblk, sc.score, sc.k, sc.flag, sc.d, sc.bmax);
+    else
+      hipLaunchKernelGGL((k_solve_top<H, float, float, B>), gr, dim3(kNT), 0, st,
+                         (const cplx<float>*)zc, (const cplx<double>*)D, mom, g, curve0, eps,
+                         hrow, k_lo, K, nblk, sc.score, sc.k, sc.flag, sc.d, sc.bmax);
+  };
+  if (g.band)
+    launch(std::true_type{});
   else
-    hipLaunchKernelGGL((k_solve_top<H, float, float>), gr, dim3(kNT), 0, st,
-                       (const cplx<float>*)zc, (const cplx<double>*)D, mom, g, curve0, eps, hrow,
-                       k_lo, K, nblk, sc.score, sc.k, sc.flag, sc.d, sc.bmax);
+    launch(std::false_type{});
   return hipGetLastError();
 }
 

@@ -307,8 +307,6 @@ class Plan:
         }
         need = int(lib().fchi2_search_top_workspace_bytes(self._h, int(K)))
         if need == 0:
-            if self.first_bin > 0:
-                raise FChi2Error(ERR_UNSUPPORTED, "band plans have no top-K epilogue")
             raise FChi2Error(ERR_ARG, "K must be in 1..64")
         ws = self.workspace(dev, need) if workspace is None else workspace
         out = TopOut(*(ctypes.c_void_p(res[k].data_ptr()) for k in

@@ -5,6 +5,8 @@ frequencies (gate and tolerance as in the other parity tests: relative error
 on max(Delta chi2, 2H') <= 1e-5 mixed, 1e-8 FP64) and against the ordinary
 search over the whole range at the same bins.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -74,14 +76,50 @@ def test_band_matches_oracle_and_the_full_search(precision, g):
     assert not np.any(fl_b[0] & F.BIN_DC)
 
 
+def _select(row, k0, df, span, hp, K):
+    """The candidate rule applied to a band's written row: strict local maxima
+    inside the row (bins 1 .. n-2 of the band), f >= 1/span, ranked by
+    ln p = ln(k0 + j) + ln Q(D | 2hp) with the bin index of the search."""
+    n = row.shape[0]
+    j = np.arange(1, n - 1)
+    j = j[((k0 + j) * df * span >= 1.0) & (row[j] > row[j - 1]) & (row[j] >= row[j + 1])]
+    u = 0.5 * np.maximum(row[j], 0.0)
+    ssum = np.zeros_like(u)
+    for q in range(hp):
+        ssum += u ** q / math.factorial(q)
+    lp = np.log(k0 + j) - u + np.log(ssum)
+    order = np.lexsort((j, lp))[:K]
+    return j[order], lp[order]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_band_top_k_equals_the_selection_from_its_rows(precision):
+    import torch
+    full = synth.make("plain", n=400, n_freq=2 ** 14, f_max=10.0)
+    g, K = 1, 12
+    nb = full.n_freq // G
+    k0 = g * nb
+    note(f"band {g} of {G} top-{K}, {precision}")
+    d, c0, _, plan = _band_search(full, precision, g)
+    t, x, s = to_dev(full)
+    r = plan.search_top(t, x, s, K=K)
+    torch.cuda.synchronize()
+    row = d[0, full.H - 1]
+    span = float(full.t[-1] - full.t[0])
+    hi, hlp = _select(row, k0, full.f_max / full.n_freq, span, full.H, K)
+    gi = r["idx"][0].cpu().numpy()
+    glp = r["log_p"][0].cpu().numpy()
+    print(f"band top-{K}: {gi[:4]} ln p {glp[:4]}", flush=True)
+    assert list(gi) == list(hi)
+    np.testing.assert_allclose(glp, hlp, rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(r["dchi2"][0].cpu().numpy().T, d[0][:, gi])
+
+
 def test_band_plan_refuses_what_it_does_not_support():
     full = synth.make("plain", n=400, n_freq=2 ** 14, f_max=10.0)
-    note("band plan: top-K refused")
+    note("band plan: shared alpha refused")
     _, _, _, plan = _band_search(full, "mixed", 2)
     t, x, s = to_dev(full)
-    with pytest.raises(F.FChi2Error) as e:
-        plan.search_top(t, x, s, K=4)
-    assert e.value.status == F.ERR_UNSUPPORTED
     import torch
     with pytest.raises(F.FChi2Error) as e:
         plan.search_multi(t, s, x.reshape(1, -1).contiguous(),
