@@ -156,3 +156,38 @@ def test_stress_band_share_full_shape():
           f"median {np.median(e):.3e}", flush=True)
     assert gate.sum() >= len(kk) - 2 and e.max() <= TOL["mixed"]
     assert abs(int(np.argmax(d[cur.H - 1])) - kp) <= 1
+
+
+def test_band_top_k_lists_merge_into_the_full_search_top_k():
+    """The all-gather step of a band split, run band after band on one GPU:
+    the K best of each band (band 0 an ordinary plan of n_freq / G bins, the
+    others band plans), merged by (ln p, bin), equal the K best of the search
+    over the whole range once the band-edge bins, which no band can rank
+    (their neighbours lie in the next band), are left out."""
+    import torch
+    full = synth.make("plain", n=400, n_freq=2 ** 14, f_max=10.0)
+    K = 12
+    nb = full.n_freq // G
+    t, x, s = to_dev(full)
+    note(f"full-range top-{2 * K}, fp64")
+    plan = F.Plan(full.offsets, full.f_max, full.H, full.n_freq, precision="fp64")
+    rf = plan.search_top(t, x, s, K=2 * K)
+    torch.cuda.synchronize()
+    edges = {g * nb for g in range(G)} | {g * nb + nb - 1 for g in range(G)}
+    fb = [int(b) for b in rf["idx"][0].cpu().numpy() if b >= 0 and int(b) not in edges][:K]
+    flp = {int(b): v for b, v in zip(rf["idx"][0].cpu().numpy(), rf["log_p"][0].cpu().numpy())}
+    cand = []
+    for g in range(G):
+        note(f"band {g} of {G} top-{K}, fp64")
+        bp = F.Plan(full.offsets, full.f_max / G, full.H, nb, precision="fp64", first_bin=g * nb)
+        r = bp.search_top(t, x, s, K=K)
+        torch.cuda.synchronize()
+        for j, lp in zip(r["idx"][0].cpu().numpy(), r["log_p"][0].cpu().numpy()):
+            if j >= 0:
+                cand.append((float(lp), g * nb + int(j)))
+    merged = sorted(cand)[:K]
+    mb = [b for _, b in merged]
+    print(f"merged bands: {mb[:6]}; full range: {fb[:6]}", flush=True)
+    assert mb == fb
+    for lp, b in merged:
+        assert abs(lp - flp[b]) <= 1e-9 * abs(flp[b])
