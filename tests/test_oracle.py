@@ -341,3 +341,58 @@ def test_detrend():
     d_raw = ora.dchi2(t, x + 5 * poly, s, [0.004], 1)["dchi2"][0, 0]
     d_det = ora.dchi2(t, ora.detrend(t, x + 5 * poly, s, 3), s, [0.004], 1)["dchi2"][0, 0]
     assert d_det < 0.1 * d_raw
+
+
+def test_scaled_condition_pins():
+    """kappa of the diagonally scaled alpha (reading of the gate, Section 3a's
+    low-frequency caveat): closed forms for 2x2, invariance under diagonal
+    scaling, and the singular limit."""
+    assert ora.scaled_condition(np.eye(5)) == pytest.approx(1.0, abs=1e-12)
+    # A diagonal matrix is perfectly conditioned once scaled, however its
+    # unscaled condition number (1e8 here) reads.
+    assert ora.scaled_condition(np.diag([1.0, 1e8, 3.0])) == pytest.approx(1.0, abs=1e-12)
+    for rho in (0.0, 0.3, -0.6, 0.99):
+        a = np.array([[1.0, rho], [rho, 1.0]])
+        want = (1.0 + abs(rho)) / (1.0 - abs(rho))
+        assert ora.scaled_condition(a) == pytest.approx(want, rel=1e-12)
+        # Scaling rows and columns by D leaves the scaled matrix unchanged.
+        D = np.diag([3.0, 0.01])
+        assert ora.scaled_condition(D @ a @ D) == pytest.approx(want, rel=1e-10)
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((40, 5))
+    a = B.T @ B
+    d = np.diag(rng.uniform(0.1, 100.0, 5))
+    assert ora.scaled_condition(d @ a @ d) == pytest.approx(ora.scaled_condition(a), rel=1e-9)
+    # Duplicated column: singular; a zero diagonal entry: infinite.
+    M = np.stack([np.ones(6), np.arange(6.0), np.ones(6)], axis=1)
+    assert ora.scaled_condition(M.T @ M) > 1e15
+    assert ora.scaled_condition(np.diag([1.0, 0.0])) == np.inf
+
+
+def test_gate_mask_hand_case():
+    """Gate of the parity tolerance: k >= 1, f >= 1/span (inclusive), and
+    kappa <= kappa_max (inclusive)."""
+    freqs = np.array([0.0, 0.05, 0.0999, 0.1, 0.2, 0.3, 0.4])
+    res = {"span": 10.0,
+           "kappa": np.array([np.inf, 1.0, 1.0, 1.0, 100.0, 100.0 + 1e-9, np.nan])}
+    got = ora.gate_mask(res, freqs, 100.0)
+    np.testing.assert_array_equal(got, [False, False, False, True, True, False, False])
+    # A curve with no span has no low-frequency cut, only the k = 0 and kappa ones.
+    res0 = {"span": 0.0, "kappa": np.array([1.0, 1.0, 1e7])}
+    np.testing.assert_array_equal(ora.gate_mask(res0, np.array([0.0, 1e-6, 5.0]), 1e6),
+                                  [False, True, False])
+
+
+def test_gate_agrees_with_flags_and_kappa():
+    """On a real curve the gate drops exactly the DC and low-frequency bins the
+    oracle flags, plus the bins whose scaled alpha is too ill-conditioned."""
+    rng = np.random.default_rng(12)
+    t, x, s = _rand_curve(rng, 60, span=20.0)
+    freqs = np.linspace(0.0, 0.5, 41)
+    res = ora.dchi2(t, x, s, freqs, 2)
+    low = (res["flags"] & (ora.FLAG_DC | ora.FLAG_LOW_F)) != 0
+    for kmax in (1e2, 1e6):
+        g = ora.gate_mask(res, freqs, kmax)
+        np.testing.assert_array_equal(g, ~low & (res["kappa"] <= kmax))
+    # The low-frequency bins of this curve are the ones below 1/span.
+    np.testing.assert_array_equal(low[1:], freqs[1:] < 1.0 / res["span"])
