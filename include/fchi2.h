@@ -71,6 +71,11 @@ typedef enum {
 /* Plan flags. */
 #define FCHI2_KEEP_FOR_BACKWARD 1u /* keep all spectra in the workspace      */
 #define FCHI2_GRAPH 2u             /* replay searches through a HIP graph    */
+#define FCHI2_FUSED_SPREAD 4u      /* spread inside the first FFT pass's
+                                      tiles (no spread grid in memory); the
+                                      results are the same bit for bit; the
+                                      autotuner may change it; not for band
+                                      plans                                  */
 
 /* Largest H supported. */
 #define FCHI2_H_MAX 8
@@ -93,9 +98,12 @@ typedef struct {
                                 fchi2_plan                                     */
   double f_max;              /* > 0: bins f_k = k f_max / n_freq, k < n_freq  */
   int32_t H;                 /* 1 .. FCHI2_H_MAX                              */
-  int64_t n_freq;            /* power of two, 2^10 .. 2^24                    */
+  int64_t n_freq;            /* power of two, 2^10 .. 2^24; or 0: chosen by
+                                fchi2_auto_n_freq(H, f_max, oversampling,
+                                max t_span) (see below)                       */
   int32_t precision;         /* fchi2_precision_t                             */
-  uint32_t flags;            /* FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH         */
+  uint32_t flags;            /* FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH |
+                                FCHI2_FUSED_SPREAD                            */
   int32_t kernel_width;      /* spreading kernel taps, 0 = default
                                 (14 for FP64, 10 for MIXED); 4..16; or 1 =
                                 floor gridding as printed in Section 3b (each
@@ -122,7 +130,26 @@ typedef struct {
                                 chi2_best and dchi2_adj per band; a band's
                                 first and last bins are never candidates), not
                                 backward, shared alpha or floor gridding      */
+  double oversampling;       /* os for n_freq = 0 (0 = default 5); > 0       */
+  const double* t_span;      /* host [n_curves]: each curve's time span
+                                (last minus first time), read only when
+                                n_freq = 0; may be NULL otherwise             */
 } fchi2_plan_desc_t;
+
+/*
+ * Trial-grid size rule used when fchi2_plan_desc_t.n_freq is 0 (Section 3a:
+ * the bin spacing must be finer than 1/(H * span) to resolve the H-th
+ * harmonic's phase over the span, and f_max is the highest frequency of
+ * interest; Section 3b sizes the arrays from the span):
+ *     n_freq = next power of two >= ceil(os * H * span * f_max),
+ * at least 2^10.  os = 5 reproduces the grids of the plain (span 100, H 3,
+ * f_max 10: 2^14) and long-curve (span 3000, H 5, f_max 50: 2^22)
+ * workloads; os >= 2 keeps 2H * span * f_max / n_freq <= 1 (no wrap of
+ * the harmonic phase within one grid period).  Pure host function.
+ * Returns 0 for non-finite or non-positive arguments, H outside
+ * 1..FCHI2_H_MAX, or a result above 2^24.
+ */
+int64_t fchi2_auto_n_freq(int32_t H, double f_max, double oversampling, double span);
 
 /*
  * Create a plan.  Validates `desc`, derives the grid geometry (grid length
@@ -135,6 +162,9 @@ typedef struct {
  * FCHI2_ERR_NOMEM, FCHI2_ERR_HIP.
  */
 fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_plan_t* out);
+
+/* Bins per curve of the plan (the derived value when desc.n_freq was 0; 0 for NULL). */
+int64_t fchi2_plan_n_freq(fchi2_plan_t plan);
 
 /* Bytes of device workspace fchi2_search / fchi2_backward need (0 for NULL). */
 size_t fchi2_workspace_bytes(fchi2_plan_t plan);
@@ -190,6 +220,28 @@ fchi2_status_t fchi2_backward(fchi2_plan_t plan, const double* t, const double* 
                               const double* sigma, const void* grad_dchi2, void* workspace,
                               size_t workspace_bytes, double* grad_x, double* grad_sigma,
                               void* stream);
+
+/*
+ * Number of searches enqueued on the plan so far (fchi2_search,
+ * fchi2_search_curves, fchi2_search_top, fchi2_search_multi and the
+ * autotuners each count one).  The workspace state fchi2_backward reads
+ * belongs to the most recent one; a caller that runs several searches on one
+ * plan records this value right after the forward it will differentiate.
+ * Returns 0 for NULL.
+ */
+uint64_t fchi2_search_generation(fchi2_plan_t plan);
+
+/*
+ * fchi2_backward for the search whose generation (fchi2_search_generation
+ * right after it) is `generation`: returns FCHI2_ERR_STATE, with no device
+ * work, if any other search has run on the plan since, so a gradient is never
+ * taken from another forward's spectra.  Arguments otherwise as
+ * fchi2_backward (which is this call with the current generation).
+ */
+fchi2_status_t fchi2_backward_at(fchi2_plan_t plan, uint64_t generation, const double* t,
+                                 const double* x, const double* sigma, const void* grad_dchi2,
+                                 void* workspace, size_t workspace_bytes, double* grad_x,
+                                 double* grad_sigma, void* stream);
 
 /*
  * Indices of the K largest strict local maxima of row `hrow` (H' = hrow + 1)
@@ -385,8 +437,9 @@ fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* 
  * Autotuner.  Times every candidate schedule of the plan on the caller's data
  * (the FFT digit splits with the fewest passes and the most balanced splits
  * with one pass more, for FP32 grids each on FFT tiles of 4096 or 8192
- * elements per pass, spreading tiles of 1024 to 8192 cells, and waves of
- * wave_max, wave_max/2, wave_max/4 curves) with HIP
+ * elements per pass, spreading tiles of 1024 to 8192 cells or, for curves of
+ * at most 8192 points outside band plans, the spreading fused into the first
+ * FFT pass, and waves of wave_max, wave_max/2, wave_max/4 curves) with HIP
  * events on `stream` (two timed runs each after a warm-up, then the three
  * fastest five more times each, in turns), keeps the fastest in the plan,
  * and appends it to the
@@ -406,7 +459,8 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
  * Current schedule of a plan: info[0] = FFT passes, info[1..4] = log2 radix of
  * digits 1..4 (0 if unused), info[5] = log2 spreading tile, info[6] = curves
  * per wave, info[7] = kernel width, and with n >= 12 info[8..11] = log2 FFT
- * tile elements of passes 1..4 (0 if unused).  n must be >= 8.
+ * tile elements of passes 1..4 (0 if unused), with n >= 13 info[12] = 1 if
+ * the spreading runs inside the first FFT pass.  n must be >= 8.
  */
 fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n);
 

@@ -22,6 +22,7 @@
 #include "fchi2_internal.h"
 #include "launch.h"
 #include "es_kernel.h"
+#include "solve_bin.h"
 
 namespace fchi2 {
 
@@ -29,35 +30,10 @@ namespace {
 
 constexpr int kNT = 256;
 
-template <int H>
-struct Layout {
-  static constexpr int P = H + (H + 1) / 2;
-};
-
-__device__ __forceinline__ double Cp(const double* Qr, int gd) { return Qr[gd < 0 ? -gd : gd]; }
-__device__ __forceinline__ double Sp(const double* Qi, int gd) {
-  return gd < 0 ? -Qi[-gd] : Qi[gd];
-}
-
-__device__ __forceinline__ double alpha_ij(int i, int j, const double* Qr, const double* Qi) {
-  if (j == 0) {
-    if (i == 0) return Qr[0];
-    const int h = (i + 1) >> 1;
-    return (i & 1) ? Qi[h] : Qr[h];
-  }
-  const int h = (i + 1) >> 1, hp = (j + 1) >> 1;
-  const bool si = (i & 1), sj = (j & 1);
-  if (si && sj) return 0.5 * (Cp(Qr, h - hp) - Cp(Qr, h + hp));
-  if (si && !sj) return 0.5 * (Sp(Qi, h + hp) + Sp(Qi, h - hp));
-  if (!si && sj) return 0.5 * (Sp(Qi, h + hp) - Sp(Qi, h - hp));
-  return 0.5 * (Cp(Qr, h - hp) + Cp(Qr, h + hp));
-}
-
-__device__ __forceinline__ double beta_i(int i, const double* Pr, const double* Pi) {
-  if (i == 0) return 0.0;
-  const int h = (i + 1) >> 1;
-  return (i & 1) ? Pi[h] : Pr[h];
-}
+// Spectra unpacking, assembly (product-to-sum) and the prefix Cholesky are
+// the forward's own (solve_bin.h), so the adjoint differentiates exactly the
+// factorisation the search used.
+using namespace solve_detail;
 
 // Add v * d alpha_ij / d(Q) for i >= j into dQr/dQi (index 0 of dQr is dW).
 __device__ __forceinline__ void alpha_adj(int i, int j, double v, double* dQr, double* dQi) {
@@ -120,73 +96,17 @@ __global__ __launch_bounds__(kNT) void k_adjoint(const cplx<R>* __restrict__ zc,
         sp[pp * L + (L - nf)] = zero;
       }
     } else {
-      // Forward spectra at bin k (same unpacking as the solve).
+      // Forward spectra, assembly and Cholesky factor at bin k, as in the solve.
       double Qr[2 * H + 1], Qi[2 * H + 1], Pr[H + 1], Pi[H + 1];
       const cplx<double> Dk = D[k];
       const double Dr = (double)Dk.x, Di = (double)Dk.y;
-      Qr[0] = mo.W;
-      Qi[0] = 0.0;
-      Pr[0] = 0.0;
-      Pi[0] = 0.0;
-#pragma unroll
-      for (int pp = 0; pp < P; ++pp) {
-        const cplx<R> z0 = zc[(((int64_t)cw * P + pp) * 2 + 0) * nf + k];
-        const cplx<R> z1 = zc[(((int64_t)cw * P + pp) * 2 + 1) * nf + k];
-        const double ax = 0.5 * ((double)z0.x + (double)z1.x);
-        const double ay = 0.5 * ((double)z0.y - (double)z1.y);
-        const double bx = 0.5 * ((double)z0.y + (double)z1.y);
-        const double by = -0.5 * ((double)z0.x - (double)z1.x);
-        const double Ar = ax * Dr - ay * Di, Ai = ax * Di + ay * Dr;
-        const double Br = bx * Dr - by * Di, Bi = bx * Di + by * Dr;
-        if (pp < H) {
-          Qr[2 * pp + 1] = Ar;
-          Qi[2 * pp + 1] = Ai;
-          Qr[2 * pp + 2] = Br;
-          Qi[2 * pp + 2] = Bi;
-        } else {
-          const int j = pp - H;
-          Pr[2 * j + 1] = Ar;
-          Pi[2 * j + 1] = Ai;
-          if (2 * j + 2 <= H) {
-            Pr[2 * j + 2] = Br;
-            Pi[2 * j + 2] = Bi;
-          }
-        }
-      }
-      // Cholesky with the forward's pivot rule.
+      load_spectra<H, R>(zc, nf, (int64_t)cw * P, k, Dk, mo.W, Qr, Qi, Pr, Pi);
       double Lm[d][d];
       double inv[d];
       double z[d];
-      static_for<0, d>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        static_for<0, i + 1>([&](auto jc) {
-          constexpr int j = decltype(jc)::value;
-          double s = alpha_ij(i, j, Qr, Qi);
-          static_for<0, j>([&](auto lc) {
-            constexpr int l = decltype(lc)::value;
-            s -= Lm[i][l] * Lm[j][l];
-          });
-          if constexpr (i == j) {
-            const double ajj = alpha_ij(i, i, Qr, Qi);
-            if (s > eps * ajj && s > 0.0) {
-              const double r = sqrt(s);
-              Lm[i][i] = r;
-              inv[i] = 1.0 / r;
-            } else {
-              Lm[i][i] = 0.0;
-              inv[i] = 0.0;
-            }
-          } else {
-            Lm[i][j] = s * inv[j];
-          }
-        });
-        double s = beta_i(i, Pr, Pi);
-        static_for<0, i>([&](auto lc) {
-          constexpr int l = decltype(lc)::value;
-          s -= Lm[i][l] * z[l];
-        });
-        z[i] = s * inv[i];
-      });
+      double dfw[H];
+      uint8_t fl = 0;
+      prefix_solve<H, double>(Qr, Qi, Pr, Pi, eps, dfw, fl, Lm, inv, z);
       // Accumulate dQ (index 0 = dW) and dP over H' = 1..H.
       double dQr[2 * H + 1], dQi[2 * H + 1], dPr[H + 1], dPi[H + 1];
       static_for<0, 2 * H + 1>([&](auto mc) {
@@ -291,7 +211,7 @@ __global__ __launch_bounds__(kNT) void k_gather(const double* __restrict__ t,
     for (int comp = 0; comp < 2; ++comp) {
       const int m = g.comp_m[p][comp];
       if (m == 0) continue;
-      const double pos = ((double)m * v) * (double)g.L + (double)g.c_off;
+      const double pos = cell_of(v, m, (double)g.L, (double)g.c_off, false);
       const double fl = floor(pos);
       const int64_t j0 = (int64_t)fl;
       const double fr = pos - fl;

@@ -1,7 +1,8 @@
 // Exponential-of-semicircle spreading kernel
 //   phi(z) = exp(beta (sqrt(1 - z^2) - 1))  for |z| < 1,  0 elsewhere,
-// evaluated with an FP64 argument by the spreading and by the adjoint's
-// gather (the same values on both sides).
+// evaluated with an FP64 argument by the spreading (standalone or fused into
+// the first FFT pass) and by the adjoint's gather (the same values
+// everywhere), and the cell coordinate of a point on a harmonic grid.
 //
 // EXACT (FP64 grids): correctly rounded FP64 sqrt and exp.
 // Otherwise (FP32 grids), with no branch:
@@ -36,6 +37,21 @@ __device__ __forceinline__ double es_kernel(double z, double beta) {
     const float p2 = ldexpf(__builtin_amdgcn_exp2f((float)(y - n)), (int)n);
     return in ? (double)p2 : 0.0;
   }
+}
+
+// Cell coordinate of a point for harmonic multiple m (FP64 phase reduction),
+// from v = (t - T0) df: m v L + c_off.  Floor gridding (kernel width 1,
+// Section 3b): the point's time is replaced by the start of its cell,
+// floor(v L), and harmonic m sits at m times that cell (an exact integer);
+// the kernel weight is then 1 at that cell only.
+__device__ __forceinline__ double cell_of(double v, int m, double L, double c_off, bool flr) {
+  if (flr) return (double)m * floor(v * L);
+  return ((double)m * v) * L + c_off;
+}
+
+__device__ __forceinline__ double cell_at(double ti, double T0, double df, int m, double L,
+                                          double c_off, bool flr) {
+  return cell_of((ti - T0) * df, m, L, c_off, flr);
 }
 
 }  // namespace fchi2

@@ -18,8 +18,17 @@
 // middle passes work in place; PASS_LAST writes natural order, pruned to the
 // bins the next stage needs.  Zero rows (grid beyond its nonzero extent, or
 // the unused middle of the adjoint spectrum) are never read.
+//
+// Fused first pass (FUSED): instead of reading the spread grid, the tile's
+// cells {g0 + cc + (L/N) r} are computed in place from the curve's points, so
+// the spreading's grid never goes through memory.  Each thread owns whole row
+// segments of the tile and sums the kernel taps of the points near them, in
+// point order, with the same kernel argument (cell - position, exact) as the
+// standalone spreading: the cell values, and so every later result, are the
+// same bit for bit.
 #include "fchi2_internal.h"
 #include "launch.h"
+#include "es_kernel.h"
 
 namespace fchi2 {
 
@@ -243,12 +252,141 @@ __device__ __forceinline__ C root(int64_t e, int logM) {
   return cmk<double>(c, s);
 }
 
+// Cells of a first-pass tile (pair p, columns g0 + cc, rows r of stride
+// Sd = L / N; rows r >= r_lim are beyond the pair's extent and stay zero)
+// spread from the curve's points straight into the LDS tile sm, as S values in
+// the tile layout (row r, column cc at r * PT + cc).  The points go through
+// LDS in chunks of 1024 as their cell coordinates on the pair's two harmonic
+// grids (computed once per point, as the spreading kernel computes them), w
+// and w (x - xbar); a thread
+// owns kEPT cells, as one segment of a row (T >= kEPT) or whole rows.  Per
+// row segment it finds the first point whose position reaches the segment
+// (binary search) and adds, point by point in index order, phi(cell - pos)
+// times the strength: component 0 of the pair into the real part (and the
+// imaginary part when both components are the same harmonic), component 1
+// into the imaginary part, as the standalone spreading does.
+template <typename S, int LOGN, int LOGT>
+__device__ __forceinline__ void spread_into_tile(const FftPassArgs& a, const Moments& mo,
+                                                 const Geom& g, int p, int64_t g0,
+                                                 int64_t r_lim, cplx<S>* sm, int tid) {
+  constexpr int N = 1 << LOGN;
+  constexpr int T = 1 << LOGT;
+  constexpr int PT = (T == 1) ? 1 : T + 1;
+  constexpr int NTH = (N * T) / kEPT;
+  constexpr int CPR = T >= kEPT ? kEPT : T;  // cells per owned row segment
+  constexpr int RPT = kEPT / CPR;            // row segments per thread
+  constexpr int TPR = T >= kEPT ? T / kEPT : 1;  // threads per row
+  constexpr bool EXACT = sizeof(S) == 8;
+  constexpr int CH = 1024;
+  static_assert(4 * CH * sizeof(double) <= N * PT * sizeof(cplx<S>), "staging exceeds the tile");
+  // Staged per point: its cell coordinate on each component's harmonic grid
+  // and the two strengths.
+  double* s_pos[2] = {(double*)sm, (double*)sm + CH};
+  double* s_w = (double*)sm + 2 * CH;
+  double* s_y = (double*)sm + 3 * CH;
+  const int64_t Sd = g.L >> LOGN;
+  int row[RPT];
+  double cell0[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    int c0;
+    if constexpr (TPR > 1) {
+      row[j] = tid / TPR;
+      c0 = (tid % TPR) * kEPT;
+    } else {
+      row[j] = tid + j * NTH;
+      c0 = 0;
+    }
+    cell0[j] = (double)(g0 + c0 + Sd * (int64_t)row[j]);
+  }
+  double ar[RPT][CPR], ai[RPT][CPR];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j)
+#pragma unroll
+    for (int u = 0; u < CPR; ++u) {
+      ar[j][u] = 0.0;
+      ai[j][u] = 0.0;
+    }
+  const int m0 = g.comp_m[p][0], m1 = g.comp_m[p][1];
+  const bool both = m1 == m0;
+  const bool has1 = m1 != 0 && !both;
+  const int k0 = g.comp_kind[p][0], k1 = g.comp_kind[p][1];
+  const bool flr = g.w == 1;
+  const double Ld = (double)g.L, coff = (double)g.c_off;
+  const double hreach = (double)(g.w / 2 + 1);
+  const double two_over_w = 2.0 / (double)g.w;
+  const double beta = g.beta;
+  const double* __restrict__ t = a.t;
+  const double* __restrict__ x = a.x;
+  const double* __restrict__ sg = a.sigma;
+  for (int64_t ch = 0; ch < mo.n; ch += CH) {
+    const int cnt = (int)((mo.n - ch) < CH ? (mo.n - ch) : CH);
+    __syncthreads();  // the previous chunk's readers are done
+    for (int q = tid; q < cnt; q += NTH) {
+      const int64_t i = mo.start + ch + q;
+      const double si = sg[i];
+      const double w = 1.0 / (si * si);
+      const double v = (t[i] - mo.T0) * g.df;
+      s_pos[0][q] = cell_of(v, m0, Ld, coff, flr);
+      if (has1) s_pos[1][q] = cell_of(v, m1, Ld, coff, flr);
+      s_w[q] = w;
+      s_y[q] = w * (x[i + mo.xshift] - mo.xbar);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+      if (comp == 0 ? m0 == 0 : !has1) continue;
+      const double* ps = s_pos[comp];
+      const double* sa = (comp ? k1 : k0) == 0 ? s_w : s_y;
+      const double* sb = (both ? k1 : 0) == 0 ? s_w : s_y;
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        if (row[j] >= r_lim) continue;
+        // first point with position >= first cell - hreach
+        const double lo = cell0[j] - hreach;
+        int qa = 0, qb = cnt;
+        while (qa < qb) {
+          const int mid = (qa + qb) >> 1;
+          if (ps[mid] < lo) qa = mid + 1;
+          else qb = mid;
+        }
+        const double hi = cell0[j] + (double)(CPR - 1) + hreach;
+        for (int q = qa; q < cnt; ++q) {
+          const double pos = ps[q];
+          if (!(pos <= hi)) break;
+          const double va = sa[q];
+          const double vb = both ? sb[q] : 0.0;
+#pragma unroll
+          for (int u = 0; u < CPR; ++u) {
+            const double phi = es_kernel<EXACT>(((cell0[j] + (double)u) - pos) * two_over_w, beta);
+            if (comp == 0) {
+              ar[j][u] += phi * va;
+              if (both) ai[j][u] += phi * vb;
+            } else {
+              ai[j][u] += phi * va;
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();  // the last chunk's readers are done
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int c0 = (TPR > 1) ? (tid % TPR) * kEPT : 0;
+#pragma unroll
+    for (int u = 0; u < CPR; ++u)
+      sm[row[j] * PT + c0 + u] = cmk<S>((S)ar[j][u], (S)ai[j][u]);
+  }
+  __syncthreads();
+}
+
 // One pass.  Twiddles between passes, for output row k of tile column cc:
 //   PASS_FIRST, np >= 3: w_M^{jd k}        (jd fixed for the tile)   = r[k]
 //   PASS_FIRST, np == 2: w_L^{(g0+cc) k}   = r[k] * small[cc k]
 //   PASS_MID:            w_M^{jd (K0+cc+Tail k)}                     = c[cc] r[k]
 // with r, c built per workgroup in FP64 and small[e] = w_L^e, e < N T.
-template <typename S, int LOGN, int LOGT>
+template <typename S, int LOGN, int LOGT, bool FUSED>
 __global__ __launch_bounds__(((1 << LOGN) << LOGT) / kEPT) void k_fft_pass(FftPassArgs a, const cplx<S>* in,
                                                  cplx<S>* out,
                                                  const Moments* __restrict__ mom, Geom g,
@@ -262,7 +400,7 @@ __global__ __launch_bounds__(((1 << LOGN) << LOGT) / kEPT) void k_fft_pass(FftPa
   constexpr bool NT = T * sizeof(cplx<S>) >= 128;
   using S0 = Stage<LOGN, LOGT, 0>;
   using SL = Stage<LOGN, LOGT, last_logns(LOGN)>;
-  __shared__ cplx<S> sm[N * PT];
+  __shared__ __align__(16) cplx<S> sm[N * PT];
   __shared__ C tr[T == 1 ? 1 : N];  // the single-pass tile has no twiddles
   __shared__ C tc[T];
   __shared__ int64_t s_rev[T];  // first pass: output offset of each tile column
@@ -296,15 +434,27 @@ __global__ __launch_bounds__(((1 << LOGN) << LOGT) / kEPT) void k_fft_pass(FftPa
       r_skip_lo = g.n_freq / Sd;
       r_skip_hi = (L - g.n_freq) / Sd;
     }
+    if constexpr (FUSED) {
+      // Forward first pass only (the launcher guarantees it).
+      spread_into_tile<S, LOGN, LOGT>(a, mo, g, p, g0, r_skip_lo, sm, tid);
 #pragma unroll
-    for (int it = 0; it < S0::PER; ++it) {
-      const int cc = S0::col(tid, it), b = S0::bfly(tid, it);
+      for (int it = 0; it < S0::PER; ++it) {
+        const int cc = S0::col(tid, it), b = S0::bfly(tid, it);
 #pragma unroll
-      for (int i = 0; i < S0::RAD; ++i) {
-        const int r = S0::in_row(b, i);
-        C val = cmk<double>(0.0, 0.0);
-        if (r < r_skip_lo || r >= r_skip_hi) val = widen(ntl<NT>(&src[g0 + cc + Sd * r]));
-        v[it * S0::RAD + i] = val;
+        for (int i = 0; i < S0::RAD; ++i)
+          v[it * S0::RAD + i] = widen(sm[S0::in_row(b, i) * PT + cc]);
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < S0::PER; ++it) {
+        const int cc = S0::col(tid, it), b = S0::bfly(tid, it);
+#pragma unroll
+        for (int i = 0; i < S0::RAD; ++i) {
+          const int r = S0::in_row(b, i);
+          C val = cmk<double>(0.0, 0.0);
+          if (r < r_skip_lo || r >= r_skip_hi) val = widen(ntl<NT>(&src[g0 + cc + Sd * r]));
+          v[it * S0::RAD + i] = val;
+        }
       }
     }
     if (a.kind == PASS_FIRST) {
@@ -438,8 +588,20 @@ hipError_t launch_one(const FftPassArgs& a, const void* in, void* out, const Mom
                       const Geom& g, const void* tws, const void* twsm, int n_curves,
                       int64_t ncols, hipStream_t st) {
   dim3 grid((unsigned)(ncols >> LOGT), (unsigned)g.P, (unsigned)n_curves);
-  hipLaunchKernelGGL((k_fft_pass<S, LOGN, LOGT>), grid, dim3(((1 << LOGN) << LOGT) / kEPT), 0, st, a,
-                     (const cplx<S>*)in, (cplx<S>*)out, mom, g, (const C*)tws, (const C*)twsm);
+  dim3 blk(((1 << LOGN) << LOGT) / kEPT);
+  if (a.fused) {
+    if (a.kind != PASS_FIRST || a.mode != MODE_FWD || g.band || !a.t || !a.x || !a.sigma)
+      return hipErrorInvalidValue;
+    if constexpr (LOGT >= 1)
+      hipLaunchKernelGGL((k_fft_pass<S, LOGN, LOGT, true>), grid, blk, 0, st, a,
+                         (const cplx<S>*)in, (cplx<S>*)out, mom, g, (const C*)tws,
+                         (const C*)twsm);
+    else
+      return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((k_fft_pass<S, LOGN, LOGT, false>), grid, blk, 0, st, a,
+                       (const cplx<S>*)in, (cplx<S>*)out, mom, g, (const C*)tws, (const C*)twsm);
+  }
   return hipGetLastError();
 }
 

@@ -42,6 +42,10 @@ fchi2_status_t hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Every first-pass tile of the fused schedule reads all of its curve's points,
+// so it is offered only for short curves.
+constexpr int64_t kFusedMaxN = 8192;
+
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 int ilog2(int64_t v) {
@@ -258,6 +262,9 @@ struct fchi2_plan_s {
   Geom g{};
   FftPlan fp{};
   int log_tile = 10;
+  // Spreading fused into the first FFT pass (no spread grid in memory);
+  // offered by the autotuner for plans of short curves (max_n <= kFusedMaxN).
+  int fused = 0;
   double eps_piv = 0.0;
   int wave = 1;
   int wave_max = 1;        // the workspace is sized for this many curves
@@ -282,6 +289,8 @@ struct fchi2_plan_s {
   size_t gkey_ws = 0;
   // backward needs a search on this workspace first
   const void* last_ws = nullptr;
+  // searches enqueued on the plan so far (the state backward reads is the last one's)
+  uint64_t gen = 0;
   // measurement: event pairs around each launch while profiling is on
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -326,9 +335,12 @@ hipError_t prof_mark(fchi2_plan_s* pl, int stage, hipStream_t st) {
     if (pe_ != hipSuccess) return hip_fail(pe_, "profiling event");    \
   } while (0)
 
+// fused_pts: the forward first pass spreads these points (t, x, sigma) in
+// its tiles instead of reading gA (null: read the spread grid).
 fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void* zc,
                            const Moments* mom, int curve0, int nw, hipStream_t st,
-                           const Geom* geom = nullptr) {
+                           const Geom* geom = nullptr,
+                           const double* const* fused_pts = nullptr) {
   const Geom& g = geom ? *geom : pl->g;
   const FftPlan& fp = pl->fp;
   FftPassArgs a{};
@@ -352,6 +364,11 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
   for (int q = fp.np; q >= 1; --q) {
     a.q = q;
     a.kind = (q == fp.np) ? PASS_FIRST : (q == 1 ? PASS_LAST : PASS_MID);
+    const bool fuse = fused_pts && a.kind == PASS_FIRST && mode == MODE_FWD;
+    a.fused = fuse ? 1 : 0;
+    a.t = fuse ? fused_pts[0] : nullptr;
+    a.x = fuse ? fused_pts[1] : nullptr;
+    a.sigma = fuse ? fused_pts[2] : nullptr;
     const int logn = fp.logn[q];
     const int logt = fp.le[q] - logn;
     const int64_t ncols = g.L >> logn;
@@ -369,6 +386,9 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
   }
   return FCHI2_OK;
 }
+
+// Whether the forward chain spreads inside the first FFT pass.
+bool use_fused(const fchi2_plan_s* pl) { return pl->fused && pl->fp.np >= 2 && !pl->g.band; }
 
 // The whole forward chain for curves [cbeg, cend), in waves of pl->wave.
 fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double* t,
@@ -388,12 +408,16 @@ fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double
     void* gA = ws + pl->off_gA;
     void* gB = ws + pl->off_gB;
     void* zc = ws + pl->off_zc + (keep ? (size_t)c0 * zc_curve : 0);
-    PROF_BEGIN(FCHI2_PROF_SPREAD);
-    e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n,
-                      (int32_t*)(ws + pl->off_tb), gA, pl->log_tile, st);
-    if (e != hipSuccess) return hip_fail(e, "spread");
-    PROF_END();
-    fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st);
+    const double* pts[3] = {t, x, sigma};
+    if (!use_fused(pl)) {
+      PROF_BEGIN(FCHI2_PROF_SPREAD);
+      e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n,
+                        (int32_t*)(ws + pl->off_tb), gA, pl->log_tile, st);
+      if (e != hipSuccess) return hip_fail(e, "spread");
+      PROF_END();
+    }
+    fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st, nullptr,
+                                   use_fused(pl) ? pts : nullptr);
     if (s != FCHI2_OK) return s;
     PROF_BEGIN(FCHI2_PROF_SOLVE);
     e = launch_solve(pl->fp64, zc, pl->d_D, mom, pl->g, c0, nw, pl->eps_piv, dchi2, flags, st);
@@ -429,12 +453,16 @@ fchi2_status_t enqueue_search_top(fchi2_plan_s* pl, const double* t, const doubl
     void* gA = ws + pl->off_gA;
     void* gB = ws + pl->off_gB;
     void* zc = ws + pl->off_zc + (keep ? (size_t)c0 * zc_curve : 0);
-    PROF_BEGIN(FCHI2_PROF_SPREAD);
-    e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n,
-                      (int32_t*)(ws + pl->off_tb), gA, pl->log_tile, st);
-    if (e != hipSuccess) return hip_fail(e, "spread");
-    PROF_END();
-    fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st);
+    const double* pts[3] = {t, x, sigma};
+    if (!use_fused(pl)) {
+      PROF_BEGIN(FCHI2_PROF_SPREAD);
+      e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n,
+                        (int32_t*)(ws + pl->off_tb), gA, pl->log_tile, st);
+      if (e != hipSuccess) return hip_fail(e, "spread");
+      PROF_END();
+    }
+    fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st, nullptr,
+                                   use_fused(pl) ? pts : nullptr);
     if (s != FCHI2_OK) return s;
     PROF_BEGIN(FCHI2_PROF_SOLVE);
     e = launch_solve_top(pl->fp64, zc, pl->d_D, mom, pl->g, c0, nw, pl->eps_piv, hrow, k_lo, K,
@@ -562,11 +590,12 @@ fchi2_status_t check_ws(fchi2_plan_s* pl, void* ws, size_t bytes) {
 // candidate tried.
 template <typename Run>
 fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
-                         const std::vector<int>& waves, Run run, hipStream_t st, float& best_ms,
-                         FftPlan& best_f, int& best_tile, int& best_wave) {
+                         const std::vector<int>& waves, bool allow_fused, Run run,
+                         hipStream_t st, float& best_ms, FftPlan& best_f, int& best_tile,
+                         int& best_wave, int& best_fused) {
   struct Cand {
     FftPlan f;
-    int tile, wave;
+    int tile, wave, fused;
     float ms;
   };
   hipEvent_t e0, e1;
@@ -582,6 +611,7 @@ fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
   auto time_one = [&](const Cand& c, float& ms) {
     pl->log_tile = c.tile;
     pl->wave = c.wave;
+    pl->fused = c.fused;
     apply_fft_plan(pl, c.f);
     hipError_t e = hipEventRecord(e0, st);
     if (e == hipSuccess) res = run();
@@ -593,8 +623,11 @@ fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
   };
   std::vector<Cand> cands;
   for (const FftPlan& f : splits)
-    for (int tile : {10, 11, 12, 13})
-      for (int wave : waves) cands.push_back(Cand{f, tile, wave, 1e30f});
+    for (int wave : waves) {
+      for (int tile : {10, 11, 12, 13}) cands.push_back(Cand{f, tile, wave, 0, 1e30f});
+      // The fused schedule has no spreading tile.
+      if (allow_fused && f.np >= 2) cands.push_back(Cand{f, 10, wave, 1, 1e30f});
+    }
   for (Cand& c : cands) {
     for (int rep = 0; rep < 3 && res == FCHI2_OK; ++rep) {
       float ms = 0.f;
@@ -623,6 +656,7 @@ fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
         best_f = cands[bi].f;
         best_tile = cands[bi].tile;
         best_wave = cands[bi].wave;
+        best_fused = cands[bi].fused;
       }
     }
   }
@@ -664,13 +698,34 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     return fail(FCHI2_ERR_ARG, "f_max must be finite and > 0");
   if (d.H < 1 || d.H > FCHI2_H_MAX)
     return fail(FCHI2_ERR_ARG, "H must be in 1..%d (got %d)", FCHI2_H_MAX, d.H);
-  if (!is_pow2(d.n_freq)) return fail(FCHI2_ERR_ARG, "n_freq must be a power of two");
-  if (d.n_freq < (1 << 10) || d.n_freq > (1 << 24))
+  int64_t n_freq = d.n_freq;
+  if (n_freq == 0) {
+    const double os = d.oversampling == 0.0 ? 5.0 : d.oversampling;
+    if (!(os > 0.0) || !std::isfinite(os))
+      return fail(FCHI2_ERR_ARG, "oversampling must be finite and > 0");
+    if (!d.t_span) return fail(FCHI2_ERR_ARG, "n_freq = 0 needs t_span (host per-curve spans)");
+    double span = 0.0;
+    for (int c = 0; c < d.n_curves; ++c) {
+      if (!(d.t_span[c] >= 0.0) || !std::isfinite(d.t_span[c]))
+        return fail(FCHI2_ERR_ARG, "t_span[%d] must be finite and >= 0", c);
+      span = d.t_span[c] > span ? d.t_span[c] : span;
+    }
+    if (!(span > 0.0)) return fail(FCHI2_ERR_ARG, "n_freq = 0 needs a curve with span > 0");
+    n_freq = fchi2_auto_n_freq(d.H, d.f_max, os, span);
+    if (n_freq == 0)
+      return fail(FCHI2_ERR_UNSUPPORTED,
+                  "n_freq from os * H * span * f_max = %.4g exceeds 2^24",
+                  os * (double)d.H * span * d.f_max);
+  }
+  if (!is_pow2(n_freq)) return fail(FCHI2_ERR_ARG, "n_freq must be a power of two");
+  if (n_freq < (1 << 10) || n_freq > (1 << 24))
     return fail(FCHI2_ERR_UNSUPPORTED, "n_freq must be in 2^10..2^24");
   if (d.precision != FCHI2_FP64 && d.precision != FCHI2_MIXED)
     return fail(FCHI2_ERR_ARG, "precision must be FCHI2_FP64 or FCHI2_MIXED");
-  if (d.flags & ~(uint32_t)(FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH))
+  if (d.flags & ~(uint32_t)(FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH | FCHI2_FUSED_SPREAD))
     return fail(FCHI2_ERR_ARG, "unknown flag bits 0x%x", d.flags);
+  if ((d.flags & FCHI2_FUSED_SPREAD) && d.first_bin > 0)
+    return fail(FCHI2_ERR_UNSUPPORTED, "band plans (first_bin > 0) spread in a kernel of their own");
   if (d.kernel_width != 0 && d.kernel_width != 1 && (d.kernel_width < 4 || d.kernel_width > 16))
     return fail(FCHI2_ERR_ARG, "kernel_width must be 0, 1 (floor gridding) or 4..16");
   if (d.kernel_width == 1 && (d.flags & FCHI2_KEEP_FOR_BACKWARD))
@@ -686,6 +741,8 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
 
   fchi2_plan_s* pl = new fchi2_plan_s();
   pl->desc = d;
+  pl->desc.n_freq = n_freq;
+  pl->desc.t_span = nullptr;  // caller memory, not kept
   pl->offsets.assign(d.offsets, d.offsets + d.n_curves + 1);
   pl->desc.offsets = pl->offsets.data();
   pl->n_total = pl->offsets.back();
@@ -695,13 +752,13 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   pl->eps_piv = pl->fp64 ? 1e-13 : 1e-6;
 
   Geom& g = pl->g;
-  g.n_freq = d.n_freq;
+  g.n_freq = n_freq;
   // Real grids of 4 n_freq cells keep bins k < n_freq (upsampling 2 over
   // [-n_freq, n_freq)); a band plan's complex grids are centred on the band,
   // whose offsets [-n_freq/2, n_freq/2) need 2 n_freq cells for the same
   // upsampling.
-  g.L = (d.first_bin > 0 ? 2 : 4) * d.n_freq;
-  g.df = d.f_max / (double)d.n_freq;
+  g.L = (d.first_bin > 0 ? 2 : 4) * n_freq;
+  g.df = d.f_max / (double)n_freq;
   g.w = d.kernel_width ? d.kernel_width : (pl->fp64 ? 14 : 10);
   g.half_w = 0.5 * g.w;
   g.beta = 2.30 * g.w;
@@ -742,6 +799,7 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     return fail(FCHI2_ERR_UNSUPPORTED, "no FFT pass split for L = 2^%d", logL);
   }
   pl->log_tile = 10;
+  pl->fused = (d.flags & FCHI2_FUSED_SPREAD) ? 1 : 0;
   apply_fft_plan(pl, pl->fp);
 
   // Waves: bound the two grid buffers to ~8 GiB unless the caller chose.
@@ -850,6 +908,19 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   return FCHI2_OK;
 }
 
+int64_t fchi2_auto_n_freq(int32_t H, double f_max, double oversampling, double span) {
+  if (H < 1 || H > FCHI2_H_MAX) return 0;
+  if (!(f_max > 0.0) || !(oversampling > 0.0) || !(span > 0.0)) return 0;
+  if (!std::isfinite(f_max) || !std::isfinite(oversampling) || !std::isfinite(span)) return 0;
+  const double want = std::ceil(oversampling * (double)H * span * f_max);
+  if (!(want <= (double)(1 << 24))) return 0;
+  int64_t n = (int64_t)1 << 10;
+  while ((double)n < want) n <<= 1;
+  return n;
+}
+
+int64_t fchi2_plan_n_freq(fchi2_plan_t plan) { return plan ? plan->g.n_freq : 0; }
+
 size_t fchi2_workspace_bytes(fchi2_plan_t plan) { return plan ? plan->ws_bytes : 0; }
 
 int64_t fchi2_total_points(fchi2_plan_t plan) { return plan ? plan->n_total : 0; }
@@ -865,6 +936,7 @@ fchi2_status_t fchi2_search(fchi2_plan_t plan, const double* t, const double* x,
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   plan->last_ws = workspace;
+  ++plan->gen;
 
   if ((plan->desc.flags & FCHI2_GRAPH) && st != nullptr && !plan->prof) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -918,14 +990,25 @@ fchi2_status_t fchi2_search_curves(fchi2_plan_t plan, int32_t first, int32_t cou
   if (s != FCHI2_OK) return s;
   // Only a search over every curve leaves a state fchi2_backward can use.
   plan->last_ws = (first == 0 && count == plan->desc.n_curves) ? workspace : nullptr;
+  ++plan->gen;
   return enqueue_search(plan, first, first + count, t, x, sigma, (char*)workspace, dchi2, chi2_0,
                         flags, (hipStream_t)stream);
 }
+
+uint64_t fchi2_search_generation(fchi2_plan_t plan) { return plan ? plan->gen : 0; }
 
 fchi2_status_t fchi2_backward(fchi2_plan_t plan, const double* t, const double* x,
                               const double* sigma, const void* grad_dchi2, void* workspace,
                               size_t workspace_bytes, double* grad_x, double* grad_sigma,
                               void* stream) {
+  return fchi2_backward_at(plan, plan ? plan->gen : 0, t, x, sigma, grad_dchi2, workspace,
+                           workspace_bytes, grad_x, grad_sigma, stream);
+}
+
+fchi2_status_t fchi2_backward_at(fchi2_plan_t plan, uint64_t generation, const double* t,
+                                 const double* x, const double* sigma, const void* grad_dchi2,
+                                 void* workspace, size_t workspace_bytes, double* grad_x,
+                                 double* grad_sigma, void* stream) {
   g_err.clear();
   if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
   if (!(plan->desc.flags & FCHI2_KEEP_FOR_BACKWARD))
@@ -936,6 +1019,11 @@ fchi2_status_t fchi2_backward(fchi2_plan_t plan, const double* t, const double* 
   if (s != FCHI2_OK) return s;
   if (plan->last_ws != workspace)
     return fail(FCHI2_ERR_STATE, "fchi2_search has not run on this workspace");
+  if (generation != plan->gen)
+    return fail(FCHI2_ERR_STATE,
+                "the workspace holds the state of search %llu, not of search %llu (another "
+                "search ran on the plan since)",
+                (unsigned long long)plan->gen, (unsigned long long)generation);
   hipStream_t st = (hipStream_t)stream;
   fchi2_plan_s* pl = plan;
   char* ws = (char*)workspace;
@@ -1024,6 +1112,7 @@ fchi2_status_t fchi2_search_top(fchi2_plan_t plan, const double* t, const double
     return fail(FCHI2_ERR_ARG, "workspace too small for K = %d: %zu < %zu bytes", K,
                 workspace_bytes, top_ws_bytes(plan, K));
   plan->last_ws = workspace;
+  ++plan->gen;
   TopOut o{out->idx, out->log_p, out->dchi2, out->dchi2_adj, out->flags, out->chi2_best,
            out->curve_flags};
   return enqueue_search_top(plan, t, x, sigma, (char*)workspace, hrow, k_lo, K, chi2_0, o,
@@ -1106,6 +1195,7 @@ fchi2_status_t fchi2_search_multi(fchi2_plan_t plan, const double* t, const doub
   if (workspace_bytes < m.bytes)
     return fail(FCHI2_ERR_ARG, "workspace too small: %zu < %zu bytes", workspace_bytes, m.bytes);
   plan->last_ws = nullptr;  // no backward for this form
+  ++plan->gen;
   return enqueue_multi(plan, m, t, sigma, x, scale, n_sources, (char*)workspace, dchi2, chi2_0,
                        flags, (hipStream_t)stream);
 }
@@ -1139,19 +1229,21 @@ fchi2_status_t fchi2_autotune_multi(fchi2_plan_t plan, const double* t, const do
   pl->prof = false;
   float best_ms = 1e30f;
   FftPlan best_f = pl->fp;
-  int best_tile = pl->log_tile, best_wave = pl->wave;
+  int best_tile = pl->log_tile, best_wave = pl->wave, best_fused = pl->fused;
   fchi2_status_t res = tune_loop(
-      pl, splits, waves,
+      pl, splits, waves, false,
       [&]() {
         return enqueue_multi(pl, multi_layout(pl, n_sources), t, sigma, x, scale, n_sources,
                              (char*)workspace, dchi2, nullptr, nullptr, st);
       },
-      st, best_ms, best_f, best_tile, best_wave);
+      st, best_ms, best_f, best_tile, best_wave, best_fused);
   pl->prof = prof;
   pl->log_tile = best_tile;
   pl->wave = best_wave;
+  pl->fused = best_fused;
   apply_fft_plan(pl, best_f);
   pl->last_ws = nullptr;
+  ++pl->gen;
   return res;
 }
 
@@ -1246,10 +1338,15 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
         const char* tag = strstr(line, " | ");
         if (!tag || strncmp(line, key, strlen(key)) != 0 || line + strlen(key) != tag) continue;
         int np = 0, ln[kMaxPasses + 1] = {0}, le[kMaxPasses + 1] = {0}, tile = 0, wave = 0;
-        if (sscanf(tag, " | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d", &np, &ln[1],
-                   &ln[2], &ln[3], &ln[4], &le[1], &le[2], &le[3], &le[4], &tile, &wave) == 11 &&
-            tile >= 10 && tile <= 13 && wave >= 1 && wave <= pl->wave_max)
+        int fz = 0;  // lines without the field name the unfused schedule
+        if (sscanf(tag, " | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d fused=%d", &np,
+                   &ln[1], &ln[2], &ln[3], &ln[4], &le[1], &le[2], &le[3], &le[4], &tile, &wave,
+                   &fz) >= 11 &&
+            tile >= 10 && tile <= 13 && wave >= 1 && wave <= pl->wave_max &&
+            (fz == 0 || (fz == 1 && !pl->g.band && pl->max_n <= kFusedMaxN))) {
           found = apply(ln, le, np, tile, wave);
+          if (found) pl->fused = fz;
+        }
       }
       fclose(fh);
       if (found) return FCHI2_OK;
@@ -1263,29 +1360,29 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
   pl->prof = false;
   float best_ms = 1e30f;
   FftPlan best_f = pl->fp;
-  int best_tile = pl->log_tile, best_wave = pl->wave;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best_tile = pl->log_tile, best_wave = pl->wave, best_fused = pl->fused;
+  const bool allow_fused = !pl->g.band && pl->max_n <= kFusedMaxN;
   fchi2_status_t res = tune_loop(
-      pl, splits, waves,
+      pl, splits, waves, allow_fused,
       [&]() {
         return enqueue_search(pl, 0, pl->desc.n_curves, t, x, sigma, (char*)workspace, dchi2,
                               nullptr, nullptr, st);
       },
-      st, best_ms, best_f, best_tile, best_wave);
-  (void)e0;
-  (void)e1;
+      st, best_ms, best_f, best_tile, best_wave, best_fused);
   pl->prof = prof;
   pl->log_tile = best_tile;
   pl->wave = best_wave;
+  pl->fused = best_fused;
   apply_fft_plan(pl, best_f);
   pl->last_ws = nullptr;
+  ++pl->gen;
   if (res != FCHI2_OK) return res;
   if (cache_path) {
     if (FILE* fh = fopen(cache_path, "a")) {
-      fprintf(fh, "%s | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d ms=%.4f\n", key,
-              best_f.np, best_f.logn[1], best_f.logn[2], best_f.logn[3], best_f.logn[4],
+      fprintf(fh, "%s | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d fused=%d ms=%.4f\n",
+              key, best_f.np, best_f.logn[1], best_f.logn[2], best_f.logn[3], best_f.logn[4],
               best_f.le[1], best_f.le[2], best_f.le[3], best_f.le[4], best_tile, best_wave,
-              best_ms);
+              best_fused, best_ms);
       fclose(fh);
     }
   }
@@ -1301,6 +1398,7 @@ fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n) {
   info[6] = plan->wave;
   info[7] = plan->g.w;
   for (int q = 1; q <= kMaxPasses && 7 + q < n; ++q) info[7 + q] = q <= plan->fp.np ? plan->fp.le[q] : 0;
+  if (n > 12) info[12] = use_fused(plan) ? 1 : 0;
   return FCHI2_OK;
 }
 

@@ -15,6 +15,10 @@ struct FftPassArgs {
   int curve0;                  // first curve of the wave
   void* zc;                    // forward: pruned spectra [wave][P][2][n_freq]
   void* grid_out;              // adjoint: natural-order grid output
+  int fused;                   // forward first pass: spread the points in the tile
+  const double* t;             // fused: the curves' points (CSR, as for the search)
+  const double* x;
+  const double* sigma;
 };
 
 // Moments, validity flags and chi2_0 of every curve: bpc workgroups per

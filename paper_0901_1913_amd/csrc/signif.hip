@@ -39,6 +39,7 @@
 #include "fchi2_internal.h"
 #include "launch.h"
 #include "solve_bin.h"
+#include "topk_keys.h"
 #include "wave_min.h"
 
 namespace fchi2 {
@@ -52,23 +53,6 @@ constexpr int kBPT = 4;
 constexpr int kSpan = kNT * kBPT;  // bins solved per block
 constexpr int kOwn = kSpan - 2;    // bins owned per block (halo on both sides)
 constexpr uint8_t kNoBin = 0xFF;   // LDS marker: bin outside 0..n_freq-1
-
-// ln Q(D | 2 hp): log of the chi2 upper tail with an even number of degrees
-// of freedom.  The partial exponential sum is evaluated by Horner's rule from
-// the highest term down (all terms are positive, so nothing cancels) and
-// log1p keeps the small-D end accurate.
-__device__ __forceinline__ double log_q_even(double d, int hp) {
-  const double u = 0.5 * (d > 0.0 ? d : 0.0);
-  double r = 1.0;
-  for (int j = hp - 1; j >= 2; --j) r = 1.0 + r * (u / (double)j);
-  const double tail = hp > 1 ? u * r : 0.0;
-  return -u + log1p(tail);
-}
-
-// (score, k) ordering: smaller score first, ties to the lower k.
-__device__ __forceinline__ bool key_less(double sa, int ia, double sb, int ib) {
-  return (sa < sb) || (sa == sb && ia < ib);
-}
 
 template <int H, typename R, typename O, bool BAND>
 __global__ __launch_bounds__(kNT) void k_solve_top(
@@ -146,7 +130,7 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
     const int i = c_slot[wv][j];
     // ln of the bin index of the search (a band plan's rows start at k0)
     const int64_t kg = (BAND ? g.k0 : 0) + B0 - 1 + i;
-    s_sc[i] = log((double)kg) + log_q_even((double)s_d[hrow][i], hp);
+    s_sc[i] = rank_score(log((double)kg) + log_q_even((double)s_d[hrow][i], hp));
   }
   __syncthreads();
   double ks[kBPT];
@@ -218,18 +202,7 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
     const double sv = w_s[L][pos];
     const int si = w_i[L][pos];
     if (sv < INFINITY) {
-      int rank = pos;
-#pragma unroll
-      for (int L2 = 0; L2 < kNT / 64; ++L2) {
-        if (L2 == L) continue;
-        int a = 0, b = K;  // first index of list L2 whose key is not smaller
-        while (a < b) {
-          const int mid = (a + b) >> 1;
-          if (key_less(w_s[L2][mid], w_i[L2][mid], sv, si)) a = mid + 1;
-          else b = mid;
-        }
-        rank += a;
-      }
+      const int rank = merged_rank(&w_s[0][0], &w_i[0][0], 64, kNT / 64, K, L, pos);
       if (rank < K) {
         s_win[rank] = si;
         wrote = true;
@@ -359,18 +332,7 @@ __global__ __launch_bounds__(kNT) void k_top_merge(
     const double sv = w_s[L][pos];
     const int sk = w_k[L][pos];
     if (sv < INFINITY) {
-      int rank = pos;
-#pragma unroll
-      for (int L2 = 0; L2 < kNT / 64; ++L2) {
-        if (L2 == L) continue;
-        int a = 0, b = K;  // first index of list L2 whose key is not smaller
-        while (a < b) {
-          const int mid = (a + b) >> 1;
-          if (key_less(w_s[L2][mid], w_k[L2][mid], sv, sk)) a = mid + 1;
-          else b = mid;
-        }
-        rank += a;
-      }
+      const int rank = merged_rank(&w_s[0][0], &w_k[0][0], 64, kNT / 64, K, L, pos);
       if (rank < K) {
         s_ws[rank] = sv;
         s_wk[rank] = sk;

@@ -181,17 +181,6 @@ __global__ __launch_bounds__(64) void k_moments_fin(const double* __restrict__ t
   if (chi2_out) chi2_out[c] = (fl & kCurveFatal) ? NAN : M2 / sc2;
 }
 
-// Cell coordinate of point i for harmonic multiple m (FP64 phase reduction).
-// Floor gridding (kernel width 1, Section 3b): the point's time is replaced by
-// the start of its cell, floor(v L), and harmonic m sits at m times that cell
-// (an exact integer); the kernel weight is then 1 at that cell only.
-__device__ __forceinline__ double cell_at(double ti, double T0, double df, int m, double L,
-                                          double c_off, bool flr) {
-  const double v = (ti - T0) * df;
-  if (flr) return (double)m * floor(v * L);
-  return ((double)m * v) * L + c_off;
-}
-
 __device__ __forceinline__ double cell_pos(const double* __restrict__ t, int64_t i, double T0,
                                            double df, int m, double L, double c_off,
                                            bool flr) {

@@ -10,11 +10,9 @@
 #include <climits>
 #include <cmath>
 
-namespace fchi2 {
+#include "topk_keys.h"
 
-__device__ __forceinline__ bool wkey_less(double sa, int ia, double sb, int ib) {
-  return (sa < sb) || (sa == sb && ia < ib);
-}
+namespace fchi2 {
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ void wmin_step(double& s, int& i) {
@@ -30,7 +28,7 @@ __device__ __forceinline__ void wmin_step(double& s, int& i) {
   b.w[0] = __builtin_amdgcn_update_dpp(id.w[0], a.w[0], CTRL, ROW_MASK, 0xF, false);
   b.w[1] = __builtin_amdgcn_update_dpp(id.w[1], a.w[1], CTRL, ROW_MASK, 0xF, false);
   const int j = __builtin_amdgcn_update_dpp(INT_MAX, i, CTRL, ROW_MASK, 0xF, false);
-  if (wkey_less(b.d, j, s, i)) {
+  if (key_less(b.d, j, s, i)) {
     s = b.d;
     i = j;
   }

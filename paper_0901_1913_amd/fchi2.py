@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfchi2.so")
 
 OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = range(6)
 FP64, MIXED = 0, 1
-KEEP_FOR_BACKWARD, GRAPH = 1, 2
+KEEP_FOR_BACKWARD, GRAPH, FUSED_SPREAD = 1, 2, 4
 H_MAX = 8
 BIN_PIVOT, BIN_LOW_F, BIN_DC = 1, 2, 4
 CURVE_NONFINITE, CURVE_UNSORTED, CURVE_WRAP, CURVE_FEW, CURVE_EMPTY = 8, 16, 32, 64, 128
@@ -33,7 +33,8 @@ EXPORTS = (
     "fchi2_search_top_workspace_bytes", "fchi2_search_top",
     "fchi2_fine_scratch_bytes", "fchi2_fine_search",
     "fchi2_search_multi_workspace_bytes", "fchi2_search_multi", "fchi2_detrend",
-    "fchi2_autotune_multi",
+    "fchi2_autotune_multi", "fchi2_search_generation", "fchi2_backward_at",
+    "fchi2_auto_n_freq", "fchi2_plan_n_freq",
 )
 PROF_STAGES = ("moments", "spread", "fft_first", "fft_mid", "fft_last", "solve",
                "bwd_solve", "bwd_fft", "bwd_gather", "bwd_final", "top_merge",
@@ -52,6 +53,8 @@ class PlanDesc(ctypes.Structure):
         ("kernel_width", ctypes.c_int32),
         ("curves_per_wave", ctypes.c_int32),
         ("first_bin", ctypes.c_int64),
+        ("oversampling", ctypes.c_double),
+        ("t_span", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -98,6 +101,10 @@ def lib() -> ctypes.CDLL:
     vp, sz, i32, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64
     L.fchi2_plan.argtypes = [ctypes.POINTER(PlanDesc), vp, ctypes.POINTER(vp)]
     L.fchi2_plan.restype = ctypes.c_int
+    L.fchi2_auto_n_freq.argtypes = [i32, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.fchi2_auto_n_freq.restype = i64
+    L.fchi2_plan_n_freq.argtypes = [vp]
+    L.fchi2_plan_n_freq.restype = i64
     L.fchi2_workspace_bytes.argtypes = [vp]
     L.fchi2_workspace_bytes.restype = sz
     L.fchi2_total_points.argtypes = [vp]
@@ -108,6 +115,10 @@ def lib() -> ctypes.CDLL:
     L.fchi2_search_curves.restype = ctypes.c_int
     L.fchi2_backward.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
     L.fchi2_backward.restype = ctypes.c_int
+    L.fchi2_backward_at.argtypes = [vp, ctypes.c_uint64, vp, vp, vp, vp, vp, sz, vp, vp, vp]
+    L.fchi2_backward_at.restype = ctypes.c_int
+    L.fchi2_search_generation.argtypes = [vp]
+    L.fchi2_search_generation.restype = ctypes.c_uint64
     L.fchi2_top_peaks_scratch_bytes.argtypes = [vp, i32]
     L.fchi2_top_peaks_scratch_bytes.restype = sz
     L.fchi2_top_peaks.argtypes = [vp, vp, i32, i64, i32, vp, sz, vp, vp]
@@ -183,6 +194,9 @@ def _dev_ptr(tensor, dtype, n=None, name="tensor"):
 class Plan:
     """A search plan: geometry, FFT split and device tables for a set of curves.
 
+    n_freq = 0 derives the grid from the spans (t_span, one per curve) and the
+    oversampling factor (default 5) by the rule of auto_n_freq.
+
     first_bin = k0 > 0 makes a band plan: its rows hold bins k0 .. k0 + n_freq - 1
     of the search with bin spacing f_max / n_freq (one share of a search split by
     frequency band); such plans support search, search_curves and autotune."""
@@ -190,7 +204,8 @@ class Plan:
     def __init__(self, offsets: Sequence[int], f_max: float, H: int, n_freq: int,
                  precision: str = "mixed", keep_for_backward: bool = False,
                  graph: bool = False, kernel_width: int = 0, curves_per_wave: int = 0,
-                 first_bin: int = 0, stream=None):
+                 first_bin: int = 0, oversampling: float = 0.0, t_span=None,
+                 fused_spread: bool = False, stream=None):
         torch = _torch()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         if off.ndim != 1 or off.shape[0] < 2:
@@ -198,21 +213,28 @@ class Plan:
         if precision not in ("mixed", "fp64"):
             raise ValueError("precision must be 'mixed' or 'fp64'")
         self._off = off
-        flags = (KEEP_FOR_BACKWARD if keep_for_backward else 0) | (GRAPH if graph else 0)
+        flags = ((KEEP_FOR_BACKWARD if keep_for_backward else 0) | (GRAPH if graph else 0)
+                 | (FUSED_SPREAD if fused_spread else 0))
         desc = PlanDesc(
             n_curves=off.shape[0] - 1,
             offsets=off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
             f_max=float(f_max), H=int(H), n_freq=int(n_freq),
             precision=FP64 if precision == "fp64" else MIXED,
             flags=flags, kernel_width=int(kernel_width), first_bin=int(first_bin),
-            curves_per_wave=int(curves_per_wave))
+            curves_per_wave=int(curves_per_wave), oversampling=float(oversampling))
+        if t_span is not None:
+            spans = np.ascontiguousarray(np.asarray(t_span, dtype=np.float64))
+            if spans.shape != (off.shape[0] - 1,):
+                raise ValueError("t_span must hold one span per curve")
+            desc.t_span = spans.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         handle = ctypes.c_void_p()
         st = _stream_handle(stream) if torch.cuda.is_available() else 0
         _check(lib().fchi2_plan(ctypes.byref(desc), ctypes.c_void_p(st), ctypes.byref(handle)))
         self._h = handle
         self.n_curves = off.shape[0] - 1
         self.n_total = int(off[-1])
-        self.H, self.n_freq, self.f_max = int(H), int(n_freq), float(f_max)
+        self.H, self.f_max = int(H), float(f_max)
+        self.n_freq = int(lib().fchi2_plan_n_freq(self._h))
         self.precision = precision
         self.first_bin = int(first_bin)
         self.keep_for_backward = keep_for_backward
@@ -448,9 +470,17 @@ class Plan:
             hw = 2.0 * hw / max(R - 1, 1)
         return res
 
+    def generation(self) -> int:
+        """Number of searches run on the plan so far (see fchi2_search_generation)."""
+        return int(lib().fchi2_search_generation(self._h))
+
     def backward(self, t, x, sigma, grad_dchi2, grad_x=None, grad_sigma=None,
-                 workspace=None, stream=None):
-        """dLoss/dx and dLoss/dsigma given dLoss/dDelta chi2 (same layout as dchi2)."""
+                 workspace=None, stream=None, generation: Optional[int] = None):
+        """dLoss/dx and dLoss/dsigma given dLoss/dDelta chi2 (same layout as dchi2).
+
+        generation: the plan's generation right after the forward search to
+        differentiate; if another search ran since, this raises (FCHI2_ERR_STATE)
+        instead of differentiating the other search.  None: the last search."""
         torch = _torch()
         f64 = torch.float64
         dev = t.device
@@ -459,8 +489,10 @@ class Plan:
         if grad_sigma is None:
             grad_sigma = torch.empty(self.n_total, dtype=f64, device=dev)
         ws = self.workspace(dev) if workspace is None else workspace
-        _check(lib().fchi2_backward(
-            self._h, _dev_ptr(t, f64, self.n_total, "t"), _dev_ptr(x, f64, self.n_total, "x"),
+        gen = self.generation() if generation is None else int(generation)
+        _check(lib().fchi2_backward_at(
+            self._h, ctypes.c_uint64(gen), _dev_ptr(t, f64, self.n_total, "t"),
+            _dev_ptr(x, f64, self.n_total, "x"),
             _dev_ptr(sigma, f64, self.n_total, "sigma"),
             _dev_ptr(grad_dchi2, self.out_dtype, self.n_curves * self.H * self.n_freq,
                      "grad_dchi2"),
@@ -502,13 +534,13 @@ class Plan:
 
     def info(self) -> dict:
         """The plan's schedule: FFT radices, spreading tile, wave, kernel width."""
-        arr = (ctypes.c_int32 * 12)()
-        _check(lib().fchi2_plan_info(self._h, arr, 12))
+        arr = (ctypes.c_int32 * 13)()
+        _check(lib().fchi2_plan_info(self._h, arr, 13))
         np_ = int(arr[0])
         return {"fft_log_radices": [int(arr[q]) for q in range(1, np_ + 1)],
                 "fft_log_tiles": [int(arr[7 + q]) for q in range(1, np_ + 1)],
                 "spread_tile": 1 << int(arr[5]), "curves_per_wave": int(arr[6]),
-                "kernel_width": int(arr[7])}
+                "kernel_width": int(arr[7]), "fused_spread": bool(arr[12])}
 
     def profile(self, enable: bool = True):
         """Start (or stop) recording HIP event pairs around every launch."""
@@ -533,6 +565,12 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def auto_n_freq(H: int, f_max: float, oversampling: float, span: float) -> int:
+    """The plan's n_freq = 0 rule: next power of two >= ceil(os H span f_max),
+    at least 2^10 (0 if out of range)."""
+    return int(lib().fchi2_auto_n_freq(int(H), float(f_max), float(oversampling), float(span)))
 
 
 def search(t, x, sigma, f_max: float, H: int, n_freq: int, precision: str = "mixed",
@@ -566,6 +604,7 @@ def _make_autograd():
                 raise ValueError("FChi2Fn needs a plan with keep_for_backward=True")
             dchi2, _, _ = plan.search(t, x, sigma, want_flags=False)
             ctx.plan = plan
+            ctx.generation = plan.generation()
             ctx.save_for_backward(t, x, sigma)
             return dchi2
 
@@ -574,7 +613,7 @@ def _make_autograd():
             t, x, sigma = ctx.saved_tensors
             plan = ctx.plan
             g = grad.to(plan.out_dtype).contiguous()
-            gx, gs = plan.backward(t, x, sigma, g)
+            gx, gs = plan.backward(t, x, sigma, g, generation=ctx.generation)
             return None, gx, gs, None
 
     return FChi2Fn

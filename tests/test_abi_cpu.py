@@ -76,6 +76,9 @@ def test_null_arguments():
     assert L.fchi2_plan(None, None, ctypes.byref(h)) == F.ERR_ARG
     assert L.fchi2_search(None, None, None, None, None, 0, None, None, None, None) == F.ERR_ARG
     assert L.fchi2_backward(None, None, None, None, None, None, 0, None, None, None) == F.ERR_ARG
+    assert L.fchi2_backward_at(None, 0, None, None, None, None, None, 0, None, None,
+                               None) == F.ERR_ARG
+    assert L.fchi2_search_generation(None) == 0
     assert L.fchi2_top_peaks(None, None, 0, 1, 1, None, 0, None, None) == F.ERR_ARG
     assert L.fchi2_search_curves(None, 0, 1, None, None, None, None, 0, None, None, None,
                                  None) == F.ERR_ARG
@@ -97,3 +100,41 @@ def test_null_arguments():
     assert L.fchi2_detrend(None, None, None, None, 1, None, None, None) == F.ERR_ARG
     assert L.fchi2_autotune_multi(None, None, None, None, None, 4, None, 0, None, None) == F.ERR_ARG
     L.fchi2_destroy(None)
+
+
+def test_auto_n_freq_rule():
+    """n_freq = 0: next power of two >= ceil(os H span f_max), at least 2^10."""
+    # The plain and long-curve workloads' grids follow from os = 5.
+    assert F.auto_n_freq(3, 10.0, 5.0, 100.0) == 2 ** 14
+    assert F.auto_n_freq(5, 50.0, 5.0, 3000.0) == 2 ** 22
+    # The paper's own density (os = 2, spacing 1/(2 H span)).
+    assert F.auto_n_freq(3, 12.0, 2.0, 1000.0) == 2 ** 17
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        H = int(rng.integers(1, F.H_MAX + 1))
+        fm, os_, sp = 10 ** rng.uniform(-1, 2), rng.uniform(0.5, 8), 10 ** rng.uniform(0, 3.5)
+        want = max(2 ** 10, 1 << int(np.ceil(np.log2(np.ceil(os_ * H * sp * fm)))))
+        got = F.auto_n_freq(H, fm, os_, sp)
+        assert got == (want if want <= 2 ** 24 else 0), (H, fm, os_, sp, got, want)
+        if got:
+            assert got >= os_ * H * sp * fm and (got == 2 ** 10 or got / 2 < np.ceil(os_ * H * sp * fm))
+    for bad in ((0, 1.0, 5.0, 1.0), (3, 0.0, 5.0, 1.0), (3, 1.0, -1.0, 1.0),
+                (3, 1.0, 5.0, float("inf")), (3, 1e6, 5.0, 1e6)):
+        assert F.auto_n_freq(*bad) == 0
+
+
+def test_plan_auto_n_freq_argument_errors():
+    off = np.array([0, 100, 250], dtype=np.int64)
+    for spans, os_, frag in ((None, 5.0, "t_span"), ([10.0, float("nan")], 5.0, "t_span[1]"),
+                             ([0.0, 0.0], 5.0, "span > 0"), ([10.0, 20.0], -2.0, "oversampling"),
+                             ([1e5, 1e5], 50.0, "exceeds")):
+        d = dict(n_curves=2, f_max=10.0, H=3, n_freq=0, precision=F.MIXED, flags=0,
+                 kernel_width=0, curves_per_wave=0, oversampling=os_)
+        desc = F.PlanDesc(offsets=off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), **d)
+        if spans is not None:
+            arr = np.asarray(spans, dtype=np.float64)
+            desc.t_span = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = ctypes.c_void_p()
+        st = F.lib().fchi2_plan(ctypes.byref(desc), None, ctypes.byref(h))
+        msg = F.lib().fchi2_last_error().decode()
+        assert st in (F.ERR_ARG, F.ERR_UNSUPPORTED) and frag in msg, (spans, st, msg)

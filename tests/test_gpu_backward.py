@@ -112,3 +112,26 @@ def test_backward_requires_keep_flag():
     with pytest.raises(F.FChi2Error) as e:
         plan.backward(t, x, s, torch.zeros_like(d))
     assert e.value.status == F.ERR_STATE
+
+
+def test_backward_of_an_older_forward_is_refused():
+    """Two forwards on one plan, then the backward of the first: the workspace
+    holds the second's spectra, so the gradient must be refused, not taken."""
+    import torch
+    cur = _diff_small("mixed")
+    note("backward of an older forward")
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed",
+                  keep_for_backward=True)
+    t, x, s = to_dev(cur)
+    Fn = F.fchi2_fn()
+    x1 = x.clone().requires_grad_(True)
+    x2 = (1.5 * x).requires_grad_(True)
+    d1 = Fn.apply(t, x1, s, plan)
+    d2 = Fn.apply(t, x2, s, plan)
+    with pytest.raises(F.FChi2Error) as e:
+        d1[0, cur.H - 1, 100:200].sum().backward()
+    assert e.value.status == F.ERR_STATE
+    # The most recent forward still differentiates.
+    d2[0, cur.H - 1, 100:200].sum().backward()
+    torch.cuda.synchronize()
+    assert torch.isfinite(x2.grad).all()

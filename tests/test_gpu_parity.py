@@ -181,3 +181,21 @@ def test_constant_data_gives_zero():
     d, c0, _, _ = run_search(cur, "fp64")
     assert abs(c0[0]) < 1e-20
     assert np.max(np.abs(d)) < 1e-12
+
+
+def test_auto_n_freq_plan_from_spans():
+    """n_freq = 0: the plan derives 2^14 bins for the plain workload (span
+    ~100 d, H = 3, f_max = 10, os = 5) and the search matches the oracle."""
+    import torch
+    cur = synth.make("plain", n=600)
+    note("plain fp64 auto n_freq")
+    span = float(cur.t[-1] - cur.t[0])
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, 0, precision="fp64", oversampling=5.0,
+                  t_span=[span])
+    assert plan.n_freq == F.auto_n_freq(cur.H, cur.f_max, 5.0, span) == 2 ** 14
+    t, x, s = to_dev(cur)
+    d, _, _ = plan.search(t, x, s)
+    torch.cuda.synchronize()
+    cur.n_freq = plan.n_freq
+    bins = sample_bins(cur.n_freq, 200, 5)
+    _check(cur, d.double().cpu().numpy(), bins, "fp64", 1e-8, label="plain auto n_freq")
