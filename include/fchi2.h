@@ -192,6 +192,26 @@ fchi2_status_t fchi2_search(fchi2_plan_t plan, const double* t, const double* x,
                             void* dchi2, double* chi2_0, uint8_t* flags, void* stream);
 
 /*
+ * fchi2_search without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  The workspace is a device array of
+ * FCHI2_NOALLOC_SCRATCH_BYTES inside the library (each device the library
+ * runs on holds one until the process ends); this call allocates nothing,
+ * makes no blocking call and never replays a graph itself (it may be
+ * captured).  Outputs and their layout are those of fchi2_search, bit for
+ * bit.  Every call on one device shares that device's array: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller.  Leaves no state for fchi2_backward.
+ * Errors: FCHI2_ERR_ARG (NULL, or fchi2_workspace_bytes(plan) above
+ * FCHI2_NOALLOC_SCRATCH_BYTES: plan fewer curves per wave or fewer bins),
+ * FCHI2_ERR_STATE (profiling on), FCHI2_ERR_HIP.
+ */
+#define FCHI2_NOALLOC_SCRATCH_BYTES (64u << 20) /* 64 MiB per device */
+fchi2_status_t fchi2_search_noalloc(fchi2_plan_t plan, const double* t, const double* x,
+                                    const double* sigma, void* dchi2, double* chi2_0,
+                                    uint8_t* flags, void* stream);
+
+/*
  * fchi2_search restricted to curves [first, first + count) of the plan: the
  * same kernels over fewer curves (count = 1 is the plain single-curve form).
  * Arguments and layouts are those of fchi2_search (full-size arrays; only the

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,6 +46,35 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Every first-pass tile of the fused schedule reads all of its curve's points,
 // so it is offered only for short curves.
 constexpr int64_t kFusedMaxN = 8192;
+
+// Workspace of fchi2_search_noalloc: a file-scope device array of
+// FCHI2_NOALLOC_SCRATCH_BYTES that every device running the library holds
+// until the process ends.  Host code never uses its name as an address: the
+// device address is looked up once per device (hipGetSymbolAddress, with that
+// device current) and kept in scratch_ptr.
+__device__ __align__(256) unsigned char scratch[FCHI2_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {nullptr};
+
+// Device address of `scratch` on the current device (looked up on first use).
+hipError_t scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -904,6 +934,11 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
       (e = hipStreamSynchronize(st)) != hipSuccess) {
     return cleanup_fail(hip_fail(e, "plan table setup"));
   }
+  // The no-allocation search's device scratch: look up its address on this
+  // device now (set-up), so that later calls only read the cached pointer.
+  void* sp = nullptr;
+  if ((e = scratch_address(&sp)) != hipSuccess)
+    return cleanup_fail(hip_fail(e, "hipGetSymbolAddress(scratch)"));
   *out = pl;
   return FCHI2_OK;
 }
@@ -974,6 +1009,29 @@ fchi2_status_t fchi2_search(fchi2_plan_t plan, const double* t, const double* x,
     }
   }
   return enqueue_search(plan, 0, plan->desc.n_curves, t, x, sigma, ws, dchi2, chi2_0, flags, st);
+}
+
+fchi2_status_t fchi2_search_noalloc(fchi2_plan_t plan, const double* t, const double* x,
+                                    const double* sigma, void* dchi2, double* chi2_0,
+                                    uint8_t* flags, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
+  if (!t || !x || !sigma || !dchi2) return fail(FCHI2_ERR_ARG, "t, x, sigma and dchi2 must not be NULL");
+  if (plan->ws_bytes > (size_t)FCHI2_NOALLOC_SCRATCH_BYTES)
+    return fail(FCHI2_ERR_ARG,
+                "plan workspace of %zu bytes exceeds the no-allocation scratch of %zu bytes "
+                "(fewer curves per wave or bins would fit)",
+                plan->ws_bytes, (size_t)FCHI2_NOALLOC_SCRATCH_BYTES);
+  if (plan->prof)
+    return fail(FCHI2_ERR_STATE, "profiling creates events; disable it for this call");
+  void* ws = nullptr;
+  HIPCHK(scratch_address(&ws));
+  // Nothing in the scratch needs to start at zero: every stage writes what the
+  // next one reads (the same contract as a fresh caller workspace).
+  plan->last_ws = nullptr;  // the scratch is not a workspace backward can be given
+  ++plan->gen;
+  return enqueue_search(plan, 0, plan->desc.n_curves, t, x, sigma, (char*)ws, dchi2, chi2_0,
+                        flags, (hipStream_t)stream);
 }
 
 fchi2_status_t fchi2_search_curves(fchi2_plan_t plan, int32_t first, int32_t count,

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libfchi2.so")
 OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = range(6)
 FP64, MIXED = 0, 1
 KEEP_FOR_BACKWARD, GRAPH, FUSED_SPREAD = 1, 2, 4
+NOALLOC_SCRATCH_BYTES = 64 << 20
 H_MAX = 8
 BIN_PIVOT, BIN_LOW_F, BIN_DC = 1, 2, 4
 CURVE_NONFINITE, CURVE_UNSORTED, CURVE_WRAP, CURVE_FEW, CURVE_EMPTY = 8, 16, 32, 64, 128
@@ -34,7 +35,7 @@ EXPORTS = (
     "fchi2_fine_scratch_bytes", "fchi2_fine_search",
     "fchi2_search_multi_workspace_bytes", "fchi2_search_multi", "fchi2_detrend",
     "fchi2_autotune_multi", "fchi2_search_generation", "fchi2_backward_at",
-    "fchi2_auto_n_freq", "fchi2_plan_n_freq",
+    "fchi2_auto_n_freq", "fchi2_plan_n_freq", "fchi2_search_noalloc",
 )
 PROF_STAGES = ("moments", "spread", "fft_first", "fft_mid", "fft_last", "solve",
                "bwd_solve", "bwd_fft", "bwd_gather", "bwd_final", "top_merge",
@@ -111,6 +112,8 @@ def lib() -> ctypes.CDLL:
     L.fchi2_total_points.restype = i64
     L.fchi2_search.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp, vp]
     L.fchi2_search.restype = ctypes.c_int
+    L.fchi2_search_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.fchi2_search_noalloc.restype = ctypes.c_int
     L.fchi2_search_curves.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp, vp, vp, vp]
     L.fchi2_search_curves.restype = ctypes.c_int
     L.fchi2_backward.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
@@ -278,6 +281,22 @@ class Plan:
         ws = self.workspace(dev) if workspace is None else workspace
         _check(lib().fchi2_search(
             self._h, pt, px, ps, ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+            _dev_ptr(dchi2, self.out_dtype, self.n_curves * self.H * self.n_freq, "dchi2"),
+            _dev_ptr(chi2_0, f64, self.n_curves, "chi2_0"),
+            _dev_ptr(flags, torch.uint8, self.n_curves * self.n_freq, "flags")
+            if flags is not None else ctypes.c_void_p(0),
+            ctypes.c_void_p(_stream_handle(stream))))
+        return dchi2, chi2_0, flags
+
+    def search_noalloc(self, t, x, sigma, dchi2, chi2_0, flags=None, stream=None):
+        """fchi2_search into caller outputs with the library's device scratch as
+        workspace (no allocation); the plan's workspace must fit in
+        NOALLOC_SCRATCH_BYTES."""
+        torch = _torch()
+        f64 = torch.float64
+        _check(lib().fchi2_search_noalloc(
+            self._h, _dev_ptr(t, f64, self.n_total, "t"), _dev_ptr(x, f64, self.n_total, "x"),
+            _dev_ptr(sigma, f64, self.n_total, "sigma"),
             _dev_ptr(dchi2, self.out_dtype, self.n_curves * self.H * self.n_freq, "dchi2"),
             _dev_ptr(chi2_0, f64, self.n_curves, "chi2_0"),
             _dev_ptr(flags, torch.uint8, self.n_curves * self.n_freq, "flags")
