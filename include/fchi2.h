@@ -71,14 +71,23 @@ typedef enum {
 /* Plan flags. */
 #define FCHI2_KEEP_FOR_BACKWARD 1u /* keep all spectra in the workspace      */
 #define FCHI2_GRAPH 2u             /* replay searches through a HIP graph    */
+#define FCHI2_WIDE_SOLVE 8u        /* solve every bin with the wave-per-bin
+                                      solver (automatic for H > 8); same
+                                      results as the register solver; no
+                                      backward or band plans                 */
 #define FCHI2_FUSED_SPREAD 4u      /* spread inside the first FFT pass's
                                       tiles (no spread grid in memory); the
                                       results are the same bit for bit; the
                                       autotuner may change it; not for band
                                       plans                                  */
 
-/* Largest H supported. */
-#define FCHI2_H_MAX 8
+/* Largest H supported by the search (fchi2_search, _curves, _coeffs,
+ * _noalloc, fchi2_autotune, fchi2_top_peaks).  Up to 8 the per-bin solve
+ * keeps the whole Cholesky factor in one thread's registers; from 9 to 16 a
+ * wave solves each bin with the matrix rows spread over its lanes.  Backward,
+ * the significance epilogue, the fine search and band plans need H <= 8
+ * (FCHI2_ERR_UNSUPPORTED otherwise); the shared-alpha search H <= 5. */
+#define FCHI2_H_MAX 16
 
 /* Per-bin flag bits (flags output of fchi2_search). */
 #define FCHI2_BIN_PIVOT 1u   /* a pivot of the normal matrix was dropped      */
@@ -87,7 +96,8 @@ typedef enum {
 /* Per-curve bits (set in every flag byte of a rejected curve). */
 #define FCHI2_CURVE_NONFINITE 8u   /* non-finite t/x/sigma or sigma <= 0     */
 #define FCHI2_CURVE_UNSORTED 16u   /* t not ascending within the curve       */
-#define FCHI2_CURVE_WRAP 32u       /* 2H * span * f_max / n_freq too large   */
+#define FCHI2_CURVE_WRAP 32u       /* harmonic phase wraps more periods than
+                                      the plan covers (see fchi2_plan)      */
 #define FCHI2_CURVE_FEW 64u        /* fewer than 2H+1 points (not fatal)     */
 #define FCHI2_CURVE_EMPTY 128u     /* no points                               */
 
@@ -103,7 +113,7 @@ typedef struct {
                                 max t_span) (see below)                       */
   int32_t precision;         /* fchi2_precision_t                             */
   uint32_t flags;            /* FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH |
-                                FCHI2_FUSED_SPREAD                            */
+                                FCHI2_FUSED_SPREAD | FCHI2_WIDE_SOLVE         */
   int32_t kernel_width;      /* spreading kernel taps, 0 = default
                                 (14 for FP64, 10 for MIXED); 4..16; or 1 =
                                 floor gridding as printed in Section 3b (each
@@ -132,8 +142,9 @@ typedef struct {
                                 backward, shared alpha or floor gridding      */
   double oversampling;       /* os for n_freq = 0 (0 = default 5); > 0       */
   const double* t_span;      /* host [n_curves]: each curve's time span
-                                (last minus first time), read only when
-                                n_freq = 0; may be NULL otherwise             */
+                                (last minus first time), or NULL; required
+                                when n_freq = 0.  Also sizes the tables for
+                                phases that wrap around the grid (below)      */
 } fchi2_plan_desc_t;
 
 /*
@@ -154,10 +165,15 @@ int64_t fchi2_auto_n_freq(int32_t H, double f_max, double oversampling, double s
 /*
  * Create a plan.  Validates `desc`, derives the grid geometry (grid length
  * L = 4 n_freq cells per harmonic grid, 2 n_freq in a band plan; Section 3b's
- * zero-padded arrays that cover at least 2H times the observed span), the FFT pass split and the
- * spreading kernel, and builds its device tables (twiddles, deconvolution) on
- * `stream`, waiting for them.  Allocates device memory for those tables
- * (owned by the plan).  On success *out receives the plan.
+ * zero-padded arrays), the FFT pass split and the spreading kernel, and
+ * builds its device tables (twiddles, deconvolution) on `stream`, waiting for
+ * them.  Allocates device memory for those tables (owned by the plan).  On
+ * success *out receives the plan.
+ * The grids are periodic: when 2H * span * f_max / n_freq exceeds 1 the
+ * harmonic phases wrap around them, which is handled (the transforms at
+ * integer bins are unchanged by whole periods); the tile tables cover enough
+ * periods for the longest span in t_span (up to 8), or 2 periods when t_span
+ * is NULL; a curve needing more is flagged FCHI2_CURVE_WRAP.
  * Errors: FCHI2_ERR_ARG (bad desc or NULL out), FCHI2_ERR_UNSUPPORTED,
  * FCHI2_ERR_NOMEM, FCHI2_ERR_HIP.
  */
@@ -210,6 +226,24 @@ fchi2_status_t fchi2_search(fchi2_plan_t plan, const double* t, const double* x,
 fchi2_status_t fchi2_search_noalloc(fchi2_plan_t plan, const double* t, const double* x,
                                     const double* sigma, void* dchi2, double* chi2_0,
                                     uint8_t* flags, void* stream);
+
+/*
+ * fchi2_search that also returns, at every bin, the coefficients of the
+ * H-harmonic fit (eq. eqcoeffs: A = alpha^-1 beta; Section 3d notes they are
+ * an intermediate result of the solve), with the weighted mean added back to
+ * A_0 (Section 3b's centring), so that the model is
+ *   x(t) = A_0 + sum_h A_{2h-1} sin(2 pi h f (t - T0)) + A_{2h} cos(2 pi h f (t - T0)),
+ * T0 the curve's first time and f = f_k (sign of Section 2's transforms).
+ *  coeffs  device [n_curves][2H+1][n_freq], float (MIXED) | double (FP64)
+ * A dropped pivot leaves its coefficient at 0; bin 0 gives A_0 = xbar and
+ * zeros; a rejected curve gives NaN.  Other arguments as fchi2_search (never
+ * replayed through a graph); leaves the state fchi2_backward reads.
+ * Errors: as fchi2_search.
+ */
+fchi2_status_t fchi2_search_coeffs(fchi2_plan_t plan, const double* t, const double* x,
+                                   const double* sigma, void* workspace, size_t workspace_bytes,
+                                   void* dchi2, double* chi2_0, uint8_t* flags, void* coeffs,
+                                   void* stream);
 
 /*
  * fchi2_search restricted to curves [first, first + count) of the plan: the
@@ -457,9 +491,9 @@ fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* 
  * Autotuner.  Times every candidate schedule of the plan on the caller's data
  * (the FFT digit splits with the fewest passes and the most balanced splits
  * with one pass more, for FP32 grids each on FFT tiles of 4096 or 8192
- * elements per pass, spreading tiles of 1024 to 8192 cells or, for curves of
- * at most 8192 points outside band plans, the spreading fused into the first
- * FFT pass, and waves of wave_max, wave_max/2, wave_max/4 curves) with HIP
+ * elements per pass, spreading tiles of 1024 to 8192 cells or, outside band
+ * plans, the spreading fused into the first FFT pass, and waves of wave_max,
+ * wave_max/2, wave_max/4 curves) with HIP
  * events on `stream` (two timed runs each after a warm-up, then the three
  * fastest five more times each, in turns), keeps the fastest in the plan,
  * and appends it to the

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kNT) void k_gather(const double* __restrict__ t,
       for (int dj = -hw - 1; dj <= hw + 1; ++dj) {
         const double phi = es_kernel<EXACT>(((double)dj - fr) * two_over_w, g.beta);
         if (phi != 0.0) {
-          const cplx<S> val = gr[j0 + dj];
+          const cplx<S> val = gr[(j0 + dj) & (g.L - 1)];  // the grid is periodic
           acc += phi * (comp == 0 ? (double)val.x : -(double)val.y);
         }
       }

@@ -10,7 +10,9 @@
 namespace fchi2 {
 
 constexpr int kHMax = 8;            // harmonics supported by the register solver
-constexpr int kMaxPairs = 24;       // 3 * kHMax (band plans: one grid per harmonic)
+constexpr int kHWide = 16;          // harmonics supported by the wave-per-bin solver
+constexpr int kMaxPairs = 24;       // 3 * kHMax (band plans: one grid per harmonic),
+                                    // = kHWide + kHWide / 2 packed pairs
 constexpr int kMaxPasses = 4;       // FFT passes (digits of the grid length)
 constexpr int kStageLog = 13;       // stage twiddle table is omega_{2^13}
 
@@ -41,7 +43,7 @@ struct MomPart {
 enum : uint32_t {
   CF_NONFINITE = 1u << 3,  // a non-finite t, x or sigma, or sigma <= 0
   CF_UNSORTED = 1u << 4,   // t not ascending
-  CF_WRAP = 1u << 5,       // 2H * df * span does not fit in one grid period
+  CF_WRAP = 1u << 5,       // 2H * df * span spans more grid periods than the plan covers
   CF_FEW = 1u << 6,        // fewer points than 2H+1 (pivots get dropped)
   CF_EMPTY = 1u << 7,      // no points
 };
@@ -100,6 +102,8 @@ struct Geom {
   int band;         // 1: band plan (first bin k0 > 0, one complex grid per harmonic,
                     //    centred on bin k0 + n_freq / 2)
   int64_t k0;       // first bin of the band (0 for the ordinary search)
+  int laps;         // grid periods the tile tables cover: positions m u L + c_off
+                    // up to laps * L (curves reaching further are flagged)
   // For pair p, component j (0 = real part, 1 = imaginary part):
   // harmonic multiple m (0 = unused) and strength kind (0: w, 1: w*(x-xbar)).
   int8_t comp_m[kMaxPairs][2];

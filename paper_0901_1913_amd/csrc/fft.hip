@@ -255,19 +255,20 @@ __device__ __forceinline__ C root(int64_t e, int logM) {
 // Cells of a first-pass tile (pair p, columns g0 + cc, rows r of stride
 // Sd = L / N; rows r >= r_lim are beyond the pair's extent and stay zero)
 // spread from the curve's points straight into the LDS tile sm, as S values in
-// the tile layout (row r, column cc at r * PT + cc).  The points go through
-// LDS in chunks of 1024 as their cell coordinates on the pair's two harmonic
-// grids (computed once per point, as the spreading kernel computes them), w
-// and w (x - xbar); a thread
-// owns kEPT cells, as one segment of a row (T >= kEPT) or whole rows.  Per
-// row segment it finds the first point whose position reaches the segment
-// (binary search) and adds, point by point in index order, phi(cell - pos)
-// times the strength: component 0 of the pair into the real part (and the
-// imaginary part when both components are the same harmonic), component 1
-// into the imaginary part, as the standalone spreading does.
-template <typename S, int LOGN, int LOGT>
+// the tile layout (row r, column cc at r * PT + cc).  A thread owns kEPT
+// cells, as one segment of a row (T >= kEPT) or whole rows.  The points that
+// can reach a segment are a contiguous index range (positions grow with t):
+// the fine tile table of the spreading (first point at or past each tile of
+// 2^tb_log cells, minus the kernel's reach) gives it with two loads, and the
+// thread reads those points, forms their cell coordinate on the component's
+// harmonic grid and strength as the spreading kernel does, and adds
+// phi(cell - pos) times the strength point by point in index order:
+// component 0 of the pair into the real part (and the imaginary part when
+// both components are the same harmonic), component 1 into the imaginary
+// part.  FLR: floor gridding (kernel width 1).
+template <typename S, int LOGN, int LOGT, bool FLR>
 __device__ __forceinline__ void spread_into_tile(const FftPassArgs& a, const Moments& mo,
-                                                 const Geom& g, int p, int64_t g0,
+                                                 const Geom& g, int p, int cw, int64_t g0,
                                                  int64_t r_lim, cplx<S>* sm, int tid) {
   constexpr int N = 1 << LOGN;
   constexpr int T = 1 << LOGT;
@@ -277,28 +278,7 @@ __device__ __forceinline__ void spread_into_tile(const FftPassArgs& a, const Mom
   constexpr int RPT = kEPT / CPR;            // row segments per thread
   constexpr int TPR = T >= kEPT ? T / kEPT : 1;  // threads per row
   constexpr bool EXACT = sizeof(S) == 8;
-  constexpr int CH = 1024;
-  static_assert(4 * CH * sizeof(double) <= N * PT * sizeof(cplx<S>), "staging exceeds the tile");
-  // Staged per point: its cell coordinate on each component's harmonic grid
-  // and the two strengths.
-  double* s_pos[2] = {(double*)sm, (double*)sm + CH};
-  double* s_w = (double*)sm + 2 * CH;
-  double* s_y = (double*)sm + 3 * CH;
   const int64_t Sd = g.L >> LOGN;
-  int row[RPT];
-  double cell0[RPT];
-#pragma unroll
-  for (int j = 0; j < RPT; ++j) {
-    int c0;
-    if constexpr (TPR > 1) {
-      row[j] = tid / TPR;
-      c0 = (tid % TPR) * kEPT;
-    } else {
-      row[j] = tid + j * NTH;
-      c0 = 0;
-    }
-    cell0[j] = (double)(g0 + c0 + Sd * (int64_t)row[j]);
-  }
   double ar[RPT][CPR], ai[RPT][CPR];
 #pragma unroll
   for (int j = 0; j < RPT; ++j)
@@ -309,74 +289,79 @@ __device__ __forceinline__ void spread_into_tile(const FftPassArgs& a, const Mom
     }
   const int m0 = g.comp_m[p][0], m1 = g.comp_m[p][1];
   const bool both = m1 == m0;
-  const bool has1 = m1 != 0 && !both;
-  const int k0 = g.comp_kind[p][0], k1 = g.comp_kind[p][1];
-  const bool flr = g.w == 1;
+  const int kd0 = g.comp_kind[p][0], kd1 = g.comp_kind[p][1];
   const double Ld = (double)g.L, coff = (double)g.c_off;
-  const double hreach = (double)(g.w / 2 + 1);
   const double two_over_w = 2.0 / (double)g.w;
   const double beta = g.beta;
   const double* __restrict__ t = a.t;
   const double* __restrict__ x = a.x;
   const double* __restrict__ sg = a.sigma;
-  for (int64_t ch = 0; ch < mo.n; ch += CH) {
-    const int cnt = (int)((mo.n - ch) < CH ? (mo.n - ch) : CH);
-    __syncthreads();  // the previous chunk's readers are done
-    for (int q = tid; q < cnt; q += NTH) {
-      const int64_t i = mo.start + ch + q;
-      const double si = sg[i];
-      const double w = 1.0 / (si * si);
-      const double v = (t[i] - mo.T0) * g.df;
-      s_pos[0][q] = cell_of(v, m0, Ld, coff, flr);
-      if (has1) s_pos[1][q] = cell_of(v, m1, Ld, coff, flr);
-      s_w[q] = w;
-      s_y[q] = w * (x[i + mo.xshift] - mo.xbar);
-    }
-    __syncthreads();
+  const int64_t pa = mo.start;
+  const double t_last = t[pa + mo.n - 1];
+  const int tbl = a.tb_log;
 #pragma unroll
-    for (int comp = 0; comp < 2; ++comp) {
-      if (comp == 0 ? m0 == 0 : !has1) continue;
-      const double* ps = s_pos[comp];
-      const double* sa = (comp ? k1 : k0) == 0 ? s_w : s_y;
-      const double* sb = (both ? k1 : 0) == 0 ? s_w : s_y;
+  for (int comp = 0; comp < 2; ++comp) {
+    const int m = comp ? m1 : m0;
+    if (m == 0 || (comp == 1 && both)) continue;
+    const int kd = comp ? kd1 : kd0;
+    const int32_t* row_tb = a.tb + ((int64_t)cw * (2 * g.H) + (m - 1)) * a.ntb;
+    // Last table entry written for harmonic m (see the spreading kernel).
+    const double last = cell_of((t_last - mo.T0) * g.df, m, Ld, coff, FLR);
+    const int64_t lim = (int64_t)floor((last + (double)(g.w / 2 + 2)) / (double)((int64_t)1 << tbl)) + 3;
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        if (row[j] >= r_lim) continue;
-        // first point with position >= first cell - hreach
-        const double lo = cell0[j] - hreach;
-        int qa = 0, qb = cnt;
-        while (qa < qb) {
-          const int mid = (qa + qb) >> 1;
-          if (ps[mid] < lo) qa = mid + 1;
-          else qb = mid;
-        }
-        const double hi = cell0[j] + (double)(CPR - 1) + hreach;
-        for (int q = qa; q < cnt; ++q) {
-          const double pos = ps[q];
-          if (!(pos <= hi)) break;
-          const double va = sa[q];
-          const double vb = both ? sb[q] : 0.0;
+    for (int j = 0; j < RPT; ++j) {
+      int row, c0;
+      if constexpr (TPR > 1) {
+        row = tid / TPR;
+        c0 = (tid % TPR) * kEPT;
+      } else {
+        row = tid + j * NTH;
+        c0 = 0;
+      }
+      if (row >= r_lim) continue;
+      const int64_t cell0 = g0 + c0 + Sd * (int64_t)row;
+      // The grid is periodic: the segment gathers its points lap after lap
+      // (positions on the unwrapped axis, table over g.laps periods).
+     for (int lap = 0; lap < g.laps; ++lap) {
+      const int64_t ucell = cell0 + (int64_t)lap * g.L;
+      const int64_t ta = ucell >> tbl, tb2 = ((ucell + CPR - 1) >> tbl) + 2;
+      if (ta > lim - 2) break;  // no point of harmonic m reaches this far
+      const int64_t lo = pa + row_tb[ta];
+      const int64_t hi = tb2 <= lim ? pa + row_tb[tb2] : pa + mo.n;
+      const double c0d = (double)ucell;
+      const double reach = (double)(g.w / 2 + 1);
+      for (int64_t i = lo; i < hi; ++i) {
+        const double pos = cell_at(t[i], mo.T0, g.df, m, Ld, coff, FLR);
+        // Only points within the kernel's reach of the segment add a nonzero
+        // tap (the others add exact zeros): skip those before it, stop after.
+        if (pos < c0d - reach) continue;
+        if (pos > c0d + (double)(CPR - 1) + reach) break;
+        const double si = sg[i];
+        const double w = 1.0 / (si * si);
+        const double wy = w * (x[i + mo.xshift] - mo.xbar);
+        const double va = kd == 0 ? w : wy;
+        const double vb = both ? (kd1 == 0 ? w : wy) : 0.0;
 #pragma unroll
-          for (int u = 0; u < CPR; ++u) {
-            const double phi = es_kernel<EXACT>(((cell0[j] + (double)u) - pos) * two_over_w, beta);
-            if (comp == 0) {
-              ar[j][u] += phi * va;
-              if (both) ai[j][u] += phi * vb;
-            } else {
-              ai[j][u] += phi * va;
-            }
+        for (int u = 0; u < CPR; ++u) {
+          const double phi = es_kernel<EXACT>(((c0d + (double)u) - pos) * two_over_w, beta);
+          if (comp == 0) {
+            ar[j][u] += phi * va;
+            if (both) ai[j][u] += phi * vb;
+          } else {
+            ai[j][u] += phi * va;
           }
         }
       }
+     }
     }
   }
-  __syncthreads();  // the last chunk's readers are done
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
+    const int row = (TPR > 1) ? tid / TPR : tid + j * NTH;
     const int c0 = (TPR > 1) ? (tid % TPR) * kEPT : 0;
 #pragma unroll
     for (int u = 0; u < CPR; ++u)
-      sm[row[j] * PT + c0 + u] = cmk<S>((S)ar[j][u], (S)ai[j][u]);
+      sm[row * PT + c0 + u] = cmk<S>((S)ar[j][u], (S)ai[j][u]);
   }
   __syncthreads();
 }
@@ -436,7 +421,10 @@ __global__ __launch_bounds__(((1 << LOGN) << LOGT) / kEPT) void k_fft_pass(FftPa
     }
     if constexpr (FUSED) {
       // Forward first pass only (the launcher guarantees it).
-      spread_into_tile<S, LOGN, LOGT>(a, mo, g, p, g0, r_skip_lo, sm, tid);
+      if (g.w == 1)
+        spread_into_tile<S, LOGN, LOGT, true>(a, mo, g, p, cw, g0, r_skip_lo, sm, tid);
+      else
+        spread_into_tile<S, LOGN, LOGT, false>(a, mo, g, p, cw, g0, r_skip_lo, sm, tid);
 #pragma unroll
       for (int it = 0; it < S0::PER; ++it) {
         const int cc = S0::col(tid, it), b = S0::bfly(tid, it);
@@ -590,7 +578,8 @@ hipError_t launch_one(const FftPassArgs& a, const void* in, void* out, const Mom
   dim3 grid((unsigned)(ncols >> LOGT), (unsigned)g.P, (unsigned)n_curves);
   dim3 blk(((1 << LOGN) << LOGT) / kEPT);
   if (a.fused) {
-    if (a.kind != PASS_FIRST || a.mode != MODE_FWD || g.band || !a.t || !a.x || !a.sigma)
+    if (a.kind != PASS_FIRST || a.mode != MODE_FWD || g.band || !a.t || !a.x || !a.sigma ||
+        !a.tb || (1 << a.tb_log) < g.w + 3)
       return hipErrorInvalidValue;
     if constexpr (LOGT >= 1)
       hipLaunchKernelGGL((k_fft_pass<S, LOGN, LOGT, true>), grid, blk, 0, st, a,

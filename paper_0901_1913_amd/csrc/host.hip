@@ -43,9 +43,13 @@ fchi2_status_t hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Every first-pass tile of the fused schedule reads all of its curve's points,
-// so it is offered only for short curves.
-constexpr int64_t kFusedMaxN = 8192;
+// Tiles of the table the fused first pass reads (2^kFusedTbLog cells, at
+// least the kernel width + 3 for every width up to 16).
+constexpr int kFusedTbLog = 5;
+
+// Most grid periods a plan's tile tables cover (curves whose harmonic phases
+// wrap further are flagged FCHI2_CURVE_WRAP).
+constexpr int kMaxLaps = 8;
 
 // Workspace of fchi2_search_noalloc: a file-scope device array of
 // FCHI2_NOALLOC_SCRATCH_BYTES that every device running the library holds
@@ -292,8 +296,7 @@ struct fchi2_plan_s {
   Geom g{};
   FftPlan fp{};
   int log_tile = 10;
-  // Spreading fused into the first FFT pass (no spread grid in memory);
-  // offered by the autotuner for plans of short curves (max_n <= kFusedMaxN).
+  // Spreading fused into the first FFT pass (no spread grid in memory).
   int fused = 0;
   double eps_piv = 0.0;
   int wave = 1;
@@ -366,11 +369,13 @@ hipError_t prof_mark(fchi2_plan_s* pl, int stage, hipStream_t st) {
   } while (0)
 
 // fused_pts: the forward first pass spreads these points (t, x, sigma) in
-// its tiles instead of reading gA (null: read the spread grid).
+// its tiles instead of reading gA (null: read the spread grid), finding them
+// through the tile table fused_tb (tiles of 2^kFusedTbLog cells).
 fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void* zc,
                            const Moments* mom, int curve0, int nw, hipStream_t st,
                            const Geom* geom = nullptr,
-                           const double* const* fused_pts = nullptr) {
+                           const double* const* fused_pts = nullptr,
+                           const int32_t* fused_tb = nullptr) {
   const Geom& g = geom ? *geom : pl->g;
   const FftPlan& fp = pl->fp;
   FftPassArgs a{};
@@ -399,6 +404,9 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
     a.t = fuse ? fused_pts[0] : nullptr;
     a.x = fuse ? fused_pts[1] : nullptr;
     a.sigma = fuse ? fused_pts[2] : nullptr;
+    a.tb = fuse ? fused_tb : nullptr;
+    a.tb_log = kFusedTbLog;
+    a.ntb = (int)((g.L >> kFusedTbLog) * g.laps) + 2;
     const int logn = fp.logn[q];
     const int logt = fp.le[q] - logn;
     const int64_t ncols = g.L >> logn;
@@ -423,7 +431,8 @@ bool use_fused(const fchi2_plan_s* pl) { return pl->fused && pl->fp.np >= 2 && !
 // The whole forward chain for curves [cbeg, cend), in waves of pl->wave.
 fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double* t,
                               const double* x, const double* sigma, char* ws, void* dchi2,
-                              double* chi2_0, uint8_t* flags, hipStream_t st) {
+                              double* chi2_0, uint8_t* flags, hipStream_t st,
+                              void* coef = nullptr) {
   Moments* mom = (Moments*)(ws + pl->off_mom);
   PROF_BEGIN(FCHI2_PROF_MOMENTS);
   hipError_t e = launch_moments(t, x, sigma, pl->d_off + cbeg, cend - cbeg, pl->mom_bpc, pl->g,
@@ -439,18 +448,21 @@ fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double
     void* gB = ws + pl->off_gB;
     void* zc = ws + pl->off_zc + (keep ? (size_t)c0 * zc_curve : 0);
     const double* pts[3] = {t, x, sigma};
-    if (!use_fused(pl)) {
-      PROF_BEGIN(FCHI2_PROF_SPREAD);
-      e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n,
-                        (int32_t*)(ws + pl->off_tb), gA, pl->log_tile, st);
-      if (e != hipSuccess) return hip_fail(e, "spread");
-      PROF_END();
-    }
+    int32_t* tb = (int32_t*)(ws + pl->off_tb);
+    PROF_BEGIN(FCHI2_PROF_SPREAD);
+    if (!use_fused(pl))
+      e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n, tb, gA,
+                        pl->log_tile, st);
+    else
+      e = launch_tile_bounds(t, mom, pl->g, c0, nw, pl->max_n, tb, kFusedTbLog, st);
+    if (e != hipSuccess) return hip_fail(e, "spread");
+    PROF_END();
     fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st, nullptr,
-                                   use_fused(pl) ? pts : nullptr);
+                                   use_fused(pl) ? pts : nullptr, tb);
     if (s != FCHI2_OK) return s;
     PROF_BEGIN(FCHI2_PROF_SOLVE);
-    e = launch_solve(pl->fp64, zc, pl->d_D, mom, pl->g, c0, nw, pl->eps_piv, dchi2, flags, st);
+    e = launch_solve(pl->fp64, zc, pl->d_D, mom, pl->g, c0, nw, pl->eps_piv, dchi2, flags, st,
+                     coef, (pl->desc.flags & FCHI2_WIDE_SOLVE) != 0);
     if (e != hipSuccess) return hip_fail(e, "solve");
     PROF_END();
   }
@@ -484,15 +496,17 @@ fchi2_status_t enqueue_search_top(fchi2_plan_s* pl, const double* t, const doubl
     void* gB = ws + pl->off_gB;
     void* zc = ws + pl->off_zc + (keep ? (size_t)c0 * zc_curve : 0);
     const double* pts[3] = {t, x, sigma};
-    if (!use_fused(pl)) {
-      PROF_BEGIN(FCHI2_PROF_SPREAD);
-      e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n,
-                        (int32_t*)(ws + pl->off_tb), gA, pl->log_tile, st);
-      if (e != hipSuccess) return hip_fail(e, "spread");
-      PROF_END();
-    }
+    int32_t* tb = (int32_t*)(ws + pl->off_tb);
+    PROF_BEGIN(FCHI2_PROF_SPREAD);
+    if (!use_fused(pl))
+      e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n, tb, gA,
+                        pl->log_tile, st);
+    else
+      e = launch_tile_bounds(t, mom, pl->g, c0, nw, pl->max_n, tb, kFusedTbLog, st);
+    if (e != hipSuccess) return hip_fail(e, "spread");
+    PROF_END();
     fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st, nullptr,
-                                   use_fused(pl) ? pts : nullptr);
+                                   use_fused(pl) ? pts : nullptr, tb);
     if (s != FCHI2_OK) return s;
     PROF_BEGIN(FCHI2_PROF_SOLVE);
     e = launch_solve_top(pl->fp64, zc, pl->d_D, mom, pl->g, c0, nw, pl->eps_piv, hrow, k_lo, K,
@@ -729,17 +743,19 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   if (d.H < 1 || d.H > FCHI2_H_MAX)
     return fail(FCHI2_ERR_ARG, "H must be in 1..%d (got %d)", FCHI2_H_MAX, d.H);
   int64_t n_freq = d.n_freq;
-  if (n_freq == 0) {
-    const double os = d.oversampling == 0.0 ? 5.0 : d.oversampling;
-    if (!(os > 0.0) || !std::isfinite(os))
-      return fail(FCHI2_ERR_ARG, "oversampling must be finite and > 0");
-    if (!d.t_span) return fail(FCHI2_ERR_ARG, "n_freq = 0 needs t_span (host per-curve spans)");
-    double span = 0.0;
+  double span = 0.0;  // longest span, if the caller gave them
+  if (d.t_span) {
     for (int c = 0; c < d.n_curves; ++c) {
       if (!(d.t_span[c] >= 0.0) || !std::isfinite(d.t_span[c]))
         return fail(FCHI2_ERR_ARG, "t_span[%d] must be finite and >= 0", c);
       span = d.t_span[c] > span ? d.t_span[c] : span;
     }
+  }
+  if (n_freq == 0) {
+    const double os = d.oversampling == 0.0 ? 5.0 : d.oversampling;
+    if (!(os > 0.0) || !std::isfinite(os))
+      return fail(FCHI2_ERR_ARG, "oversampling must be finite and > 0");
+    if (!d.t_span) return fail(FCHI2_ERR_ARG, "n_freq = 0 needs t_span (host per-curve spans)");
     if (!(span > 0.0)) return fail(FCHI2_ERR_ARG, "n_freq = 0 needs a curve with span > 0");
     n_freq = fchi2_auto_n_freq(d.H, d.f_max, os, span);
     if (n_freq == 0)
@@ -752,8 +768,13 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     return fail(FCHI2_ERR_UNSUPPORTED, "n_freq must be in 2^10..2^24");
   if (d.precision != FCHI2_FP64 && d.precision != FCHI2_MIXED)
     return fail(FCHI2_ERR_ARG, "precision must be FCHI2_FP64 or FCHI2_MIXED");
-  if (d.flags & ~(uint32_t)(FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH | FCHI2_FUSED_SPREAD))
+  if (d.flags & ~(uint32_t)(FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH | FCHI2_FUSED_SPREAD |
+                            FCHI2_WIDE_SOLVE))
     return fail(FCHI2_ERR_ARG, "unknown flag bits 0x%x", d.flags);
+  if ((d.H > kHMax || (d.flags & FCHI2_WIDE_SOLVE)) && (d.flags & FCHI2_KEEP_FOR_BACKWARD))
+    return fail(FCHI2_ERR_UNSUPPORTED, "backward needs H <= %d (the register solver)", kHMax);
+  if ((d.H > kHMax || (d.flags & FCHI2_WIDE_SOLVE)) && d.first_bin > 0)
+    return fail(FCHI2_ERR_UNSUPPORTED, "band plans need H <= %d (the register solver)", kHMax);
   if ((d.flags & FCHI2_FUSED_SPREAD) && d.first_bin > 0)
     return fail(FCHI2_ERR_UNSUPPORTED, "band plans (first_bin > 0) spread in a kernel of their own");
   if (d.kernel_width != 0 && d.kernel_width != 1 && (d.kernel_width < 4 || d.kernel_width > 16))
@@ -793,6 +814,18 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   g.half_w = 0.5 * g.w;
   g.beta = 2.30 * g.w;
   g.c_off = g.w == 1 ? 0 : g.w / 2 + 2;
+  // Grid periods the tile tables cover.  The phase m u of harmonic m runs
+  // over m df span cycles: beyond one cycle it wraps around the periodic grid
+  // (Section 3b sizes its arrays to cover 2H times the span, which holds only
+  // for a fine enough grid).  With the spans known, exactly what the longest
+  // curve needs (at most kMaxLaps); otherwise two periods.
+  g.laps = 2;
+  if (span > 0.0) {
+    const double reach = (2.0 * d.H) * span * (d.f_max / (double)n_freq) * (double)g.L +
+                         (double)g.c_off + (double)(g.w / 2) + 3.0;
+    const double lp = std::floor(reach / (double)g.L) + 1.0;
+    g.laps = (int)std::min<double>(std::max<double>(lp, 1.0), (double)kMaxLaps);
+  }
   g.H = d.H;
   g.band = d.first_bin > 0 ? 1 : 0;
   g.k0 = d.first_bin;
@@ -858,8 +891,9 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   pl->off_part = off;
   off = align256(off + sizeof(MomPart) * (size_t)d.n_curves * pl->mom_bpc);
   pl->off_tb = off;
-  // Sized for the smallest spreading tile the autotuner may pick.
-  off = align256(off + tile_bounds_bytes(g, 10, pl->wave));
+  // Sized for the finest table: the fused first pass's tiles of 2^kFusedTbLog
+  // cells (the spreading kernel's tiles are 2^10 cells or more).
+  off = align256(off + tile_bounds_bytes(g, kFusedTbLog, pl->wave));
   pl->off_gA = off;
   off = align256(off + grid_curve * pl->wave);
   pl->off_gB = off;
@@ -1034,6 +1068,22 @@ fchi2_status_t fchi2_search_noalloc(fchi2_plan_t plan, const double* t, const do
                         flags, (hipStream_t)stream);
 }
 
+fchi2_status_t fchi2_search_coeffs(fchi2_plan_t plan, const double* t, const double* x,
+                                   const double* sigma, void* workspace, size_t workspace_bytes,
+                                   void* dchi2, double* chi2_0, uint8_t* flags, void* coeffs,
+                                   void* stream) {
+  g_err.clear();
+  if (!plan) return fail(FCHI2_ERR_ARG, "plan is NULL");
+  if (!t || !x || !sigma || !dchi2 || !coeffs)
+    return fail(FCHI2_ERR_ARG, "t, x, sigma, dchi2 and coeffs must not be NULL");
+  fchi2_status_t s = check_ws(plan, workspace, workspace_bytes);
+  if (s != FCHI2_OK) return s;
+  plan->last_ws = workspace;
+  ++plan->gen;
+  return enqueue_search(plan, 0, plan->desc.n_curves, t, x, sigma, (char*)workspace, dchi2,
+                        chi2_0, flags, (hipStream_t)stream, coeffs);
+}
+
 fchi2_status_t fchi2_search_curves(fchi2_plan_t plan, int32_t first, int32_t count,
                                    const double* t, const double* x, const double* sigma,
                                    void* workspace, size_t workspace_bytes, void* dchi2,
@@ -1164,6 +1214,8 @@ fchi2_status_t fchi2_search_top(fchi2_plan_t plan, const double* t, const double
   if (K < 1 || K > 64) return fail(FCHI2_ERR_ARG, "K must be in 1..64");
   if (hrow < 0 || hrow >= plan->g.H) return fail(FCHI2_ERR_ARG, "hrow must be in 0..H-1");
   if (k_lo < 0) return fail(FCHI2_ERR_ARG, "k_lo must be >= 0");
+  if (plan->g.H > kHMax)
+    return fail(FCHI2_ERR_UNSUPPORTED, "the significance epilogue needs H <= %d", kHMax);
   fchi2_status_t s = check_ws(plan, workspace, workspace_bytes);
   if (s != FCHI2_OK) return s;
   if (workspace_bytes < top_ws_bytes(plan, K))
@@ -1197,6 +1249,8 @@ fchi2_status_t fchi2_fine_search(fchi2_plan_t plan, const double* t, const doubl
                 "t, x, sigma, f_center, out, out->f_best and out->dchi2_best must not be NULL");
   if (K < 1 || K > 256) return fail(FCHI2_ERR_ARG, "K must be in 1..256");
   if (R < 1 || R > 4096) return fail(FCHI2_ERR_ARG, "R must be in 1..4096");
+  if (plan->g.H > kHMax)
+    return fail(FCHI2_ERR_UNSUPPORTED, "the fine search needs H <= %d", kHMax);
   if (!(half_width >= 0.0) || !std::isfinite(half_width))
     return fail(FCHI2_ERR_ARG, "half_width must be finite and >= 0");
   if (hrow < 0 || hrow >= plan->g.H) return fail(FCHI2_ERR_ARG, "hrow must be in 0..H-1");
@@ -1401,7 +1455,7 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
                    &ln[1], &ln[2], &ln[3], &ln[4], &le[1], &le[2], &le[3], &le[4], &tile, &wave,
                    &fz) >= 11 &&
             tile >= 10 && tile <= 13 && wave >= 1 && wave <= pl->wave_max &&
-            (fz == 0 || (fz == 1 && !pl->g.band && pl->max_n <= kFusedMaxN))) {
+            (fz == 0 || (fz == 1 && !pl->g.band))) {
           found = apply(ln, le, np, tile, wave);
           if (found) pl->fused = fz;
         }
@@ -1419,7 +1473,7 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
   float best_ms = 1e30f;
   FftPlan best_f = pl->fp;
   int best_tile = pl->log_tile, best_wave = pl->wave, best_fused = pl->fused;
-  const bool allow_fused = !pl->g.band && pl->max_n <= kFusedMaxN;
+  const bool allow_fused = !pl->g.band;
   fchi2_status_t res = tune_loop(
       pl, splits, waves, allow_fused,
       [&]() {

@@ -19,6 +19,9 @@ struct FftPassArgs {
   const double* t;             // fused: the curves' points (CSR, as for the search)
   const double* x;
   const double* sigma;
+  const int32_t* tb;           // fused: tile table of tiles of 2^tb_log cells
+  int tb_log;                  //   (2^tb_log >= w + 3), ntb entries per harmonic
+  int ntb;
 };
 
 // Moments, validity flags and chi2_0 of every curve: bpc workgroups per
@@ -38,6 +41,11 @@ hipError_t launch_spread(bool fp64, const double* t, const double* x, const doub
                          int64_t max_n, int32_t* tb, void* grid, int log_tile, hipStream_t st,
                          bool share_tb = false);
 size_t tile_bounds_bytes(const Geom& g, int log_tile, int n_curves);
+// The tile table alone (tiles of 2^log_tile cells): the fused first FFT pass
+// reads it to find each row segment's points.
+hipError_t launch_tile_bounds(const double* t, const Moments* mom, const Geom& g, int curve0,
+                              int n_curves, int64_t max_n, int32_t* tb, int log_tile,
+                              hipStream_t st);
 
 // log2 of the elements of the largest FFT tile (rows x columns held in LDS).
 int fft_tile_log(bool fp64);
@@ -51,10 +59,14 @@ hipError_t launch_fft_pass(bool fp64, const FftPassArgs& a, int logn, int logt, 
 hipError_t launch_deconv_init(void* D, const Geom& g, const double* gl_x, const double* gl_w,
                               int n_gl, hipStream_t st);
 
-// Normal-matrix assembly, Cholesky and prefix Delta chi2 per bin.
+// Normal-matrix assembly, Cholesky and prefix Delta chi2 per bin; coef
+// (nullable): the H model's coefficients [curve][2H+1][n_freq], output type.
+// H <= 8 uses the register solver (one bin per thread) unless `wide`; H > 8
+// always the wave-per-bin solver (H <= 16, not for band plans).
 hipError_t launch_solve(bool fp64, const void* zc, const void* D, const Moments* mom,
                         const Geom& g, int curve0, int n_curves, double eps_piv, void* dchi2,
-                        uint8_t* flags, hipStream_t st);
+                        uint8_t* flags, hipStream_t st, void* coef = nullptr,
+                        bool wide = false);
 
 // Shared-alpha solve for sources at the same times (H <= 5): alpha from the
 // weight spectra zq (slot 0, H pairs), beta per source from zp (ceil(H/2)

@@ -294,17 +294,26 @@ __device__ __forceinline__ void load_p(const cplx<R>* __restrict__ zc, int64_t n
 // Delta chi2 of bin k of curve c (wave slot cw) for H' = 1..H, rounded to the
 // output type, into d[0..H-1]; returns the bin's flags.  Curves with a fatal
 // data flag give NaN rows; bin 0 gives zero rows and the DC flag.  BAND: a
-// band plan's grids (bin k is bin k0 + k of the search).
-template <int H, typename R, typename O, bool BAND = false>
+// band plan's grids (bin k is bin k0 + k of the search).  COEF: also the
+// coefficients of the H-harmonic model into A[0..2H] (eq. eqcoeffs,
+// A = alpha^-1 beta by back substitution L^T A = z, basis [1, sin, cos, ...]
+// in tau = t - T0), with the weighted mean added back to A_0 (Section 3b's
+// centring); a dropped pivot's coefficient is 0; bin 0 gives A_0 = xbar and
+// zeros; a rejected curve gives NaN.
+template <int H, typename R, typename O, bool BAND = false, bool COEF = false>
 __device__ __forceinline__ uint8_t solve_bin(const cplx<R>* __restrict__ zc,
                                              const cplx<double>* __restrict__ D,
                                              const Moments& mo, const Geom& g, int cw, int64_t k,
-                                             double eps, O* d) {
+                                             double eps, O* d, double* A = nullptr) {
   constexpr int dd = 2 * H + 1;
   constexpr int P = Layout<H>::P;
   if (mo.flags & kCurveFatal) {
 #pragma unroll
     for (int h = 0; h < H; ++h) d[h] = nan_of<O>();
+    if constexpr (COEF) {
+#pragma unroll
+      for (int j = 0; j < dd; ++j) A[j] = (double)NAN;
+    }
     return (uint8_t)(mo.flags & 0xF8u);
   }
   uint8_t fl = 0;
@@ -314,6 +323,11 @@ __device__ __forceinline__ uint8_t solve_bin(const cplx<R>* __restrict__ zc,
   if (kg == 0) {
 #pragma unroll
     for (int h = 0; h < H; ++h) d[h] = (O)0;
+    if constexpr (COEF) {
+      A[0] = mo.xbar;
+#pragma unroll
+      for (int j = 1; j < dd; ++j) A[j] = 0.0;
+    }
     return (uint8_t)(fl | BF_DC);
   }
   double Qr[2 * H + 1], Qi[2 * H + 1], Pr[H + 1], Pi[H + 1];
@@ -325,6 +339,18 @@ __device__ __forceinline__ uint8_t solve_bin(const cplx<R>* __restrict__ zc,
   double inv[dd];
   double z[dd];
   prefix_solve<H, O>(Qr, Qi, Pr, Pi, eps, d, fl, Lm, inv, z);
+  if constexpr (COEF) {
+    static_for<0, dd>([&](auto rc) {
+      constexpr int ii = dd - 1 - decltype(rc)::value;
+      double sacc = z[ii];
+      static_for<ii + 1, dd>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        sacc -= Lm[l][ii] * A[l];
+      });
+      A[ii] = sacc * inv[ii];
+    });
+    A[0] += mo.xbar;
+  }
   return fl;
 }
 

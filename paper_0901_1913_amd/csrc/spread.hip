@@ -10,9 +10,11 @@
 // grid of L = 4 * n_freq cells at cell coordinate u * L + c_off, so that one
 // FFT per grid gives all n_freq bins (the grid replaces the paper's Kronecker
 // gridding of Section 3b; the kernel's Fourier transform is divided out
-// afterwards).  Requiring 2H * df * span < 1 (the grid spans at least 2H times
-// the observed period, Section 3b) means u never wraps, so positions are
-// monotone in t and a tile of cells owns a contiguous range of points.
+// afterwards).  The grid is periodic: when 2H * df * span exceeds 1 (the
+// arrays of Section 3b cover fewer than 2H times the observed span) the
+// phases m u wrap around it.  Positions are kept unwrapped, so they grow with
+// t and every tile of cells owns a contiguous range of points in each period
+// ("lap") of the grid; the tile table runs over the plan's laps.
 //
 // Two real grids are packed per complex grid (real part, imaginary part);
 // each workgroup owns a tile of cells of one packed grid and sums the kernel
@@ -163,9 +165,10 @@ __global__ __launch_bounds__(64) void k_moments_fin(const double* __restrict__ t
   }
   if (n < 2 * g.H + 1) fl |= CF_FEW;
   if (!(fl & kCurveFatal)) {
+    // The tile tables cover g.laps periods of the grid.
     const double v = m.span * g.df;
     const double pos = ((double)(2 * g.H) * v) * (double)g.L + (double)g.c_off;
-    if (!(pos + (double)(g.w / 2) + 3.0 <= (double)g.L)) fl |= CF_WRAP;
+    if (!(pos + (double)(g.w / 2) + 3.0 <= (double)g.laps * (double)g.L)) fl |= CF_WRAP;
   }
   // A source whose errors are scale[c] times the shared sigma: its chi2 is the
   // base-weight sum divided by scale^2 (the weights are sigma^-2 / scale^2).
@@ -290,27 +293,27 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
     acc_im[u] = 0.0;
   }
 
-  // Point ranges of both components, loaded together before either is staged.
-  int64_t rng_lo[2] = {0, 0}, rng_hi[2] = {0, 0};
-#pragma unroll
+  // The grid is periodic in L cells: positions are kept unwrapped (the
+  // phase m u of a long curve may span several periods) and the tile table
+  // runs over g.laps periods, so the tile gathers its points lap after lap
+  // (in index order: positions grow with t).
+  const int64_t ntile = g.L >> LOGB;
   for (int comp = 0; comp < 2; ++comp) {
     const int m = g.comp_m[p][comp];
     if (m == 0) continue;
     if (comp == 1 && m == g.comp_m[p][0]) continue;  // shared with component 0
-    // No point of harmonic m reaches tiles past tile_limit - 2.
-    if (tile + 2 > tile_limit_of(t_last, mo, g, m, LOGB)) continue;
-    const int32_t* row = tb + ((int64_t)(share_tb ? 0 : cw) * (2 * g.H) + (m - 1)) * ntb;
-    rng_lo[comp] = pa + row[tile];
-    rng_hi[comp] = pa + row[tile + 2];
-  }
-
-  for (int comp = 0; comp < 2; ++comp) {
-    const int m = g.comp_m[p][comp];
-    const int64_t i_lo = rng_lo[comp], i_hi = rng_hi[comp];
-    if (i_hi <= i_lo) continue;  // no points (or component absent / shared)
     const bool both = (comp == 0) && (g.comp_m[p][1] == m);
     const int kind_a = g.comp_kind[p][comp];
     const int kind_b = both ? g.comp_kind[p][1] : -1;
+    const int32_t* row = tb + ((int64_t)(share_tb ? 0 : cw) * (2 * g.H) + (m - 1)) * ntb;
+    // No point of harmonic m reaches tiles past tile_limit - 2.
+    const int64_t lim = tile_limit_of(t_last, mo, g, m, LOGB);
+   for (int lap = 0; lap < g.laps; ++lap) {
+    const int64_t ut = tile + (int64_t)lap * ntile;  // tile on the unwrapped axis
+    if (ut + 2 > lim) break;
+    const int64_t i_lo = pa + row[ut], i_hi = pa + row[ut + 2];
+    if (i_hi <= i_lo) continue;  // no points in this lap
+    const int64_t base = a0 + (int64_t)lap * g.L;
 
     for (int64_t ch = i_lo; ch < i_hi; ch += CH) {
       const int cnt = (int)((i_hi - ch) < CH ? (i_hi - ch) : CH);
@@ -347,9 +350,9 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
           sre = 0.0;
           sim = sa;
         }
-        // pos - a0 is exact (a multiple of pos's ulp, smaller than pos), and
-        // so is jl - s_p below: the same kernel argument as jl - cell - frac.
-        s_p[q] = pos - (double)a0;
+        // pos - base is exact (a multiple of pos's ulp, smaller than pos),
+        // and so is jl - s_p below: the same kernel argument as jl - cell - frac.
+        s_p[q] = pos - (double)base;
         s_v[q] = make_double2(sre, sim);
       }
       __syncthreads();
@@ -390,6 +393,7 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
       }
       __syncthreads();
     }
+   }
   }
 
   cplx<S>* out = grid + ((int64_t)cw * g.P + p) * g.L + a0;
@@ -439,7 +443,7 @@ hipError_t launch_spread(bool fp64, const double* t, const double* x, const doub
                          int64_t max_n, int32_t* tb, void* grid, int log_tile, hipStream_t st,
                          bool share_tb) {
   const int64_t tiles = g.L >> log_tile;
-  const int ntb = (int)tiles + 2;
+  const int ntb = (int)(tiles * g.laps) + 2;
   dim3 gb((unsigned)((max_n + 1 + kNT - 1) / kNT), (unsigned)(2 * g.H), (unsigned)n_curves);
   // Sources sharing one time base share the table of slot 0 (built already).
   if (!share_tb)
@@ -476,9 +480,18 @@ hipError_t launch_spread(bool fp64, const double* t, const double* x, const doub
   return hipGetLastError();
 }
 
+hipError_t launch_tile_bounds(const double* t, const Moments* mom, const Geom& g, int curve0,
+                              int n_curves, int64_t max_n, int32_t* tb, int log_tile,
+                              hipStream_t st) {
+  const int ntb = (int)((g.L >> log_tile) * g.laps) + 2;
+  dim3 gb((unsigned)((max_n + 1 + kNT - 1) / kNT), (unsigned)(2 * g.H), (unsigned)n_curves);
+  hipLaunchKernelGGL(k_tile_bounds, gb, dim3(kNT), 0, st, t, mom, g, curve0, log_tile, ntb, tb);
+  return hipGetLastError();
+}
+
 size_t tile_bounds_bytes(const Geom& g, int log_tile, int n_curves) {
   return sizeof(int32_t) * (size_t)n_curves * (size_t)(2 * g.H) *
-         (size_t)((g.L >> log_tile) + 2);
+         (size_t)((g.L >> log_tile) * g.laps + 2);
 }
 
 hipError_t launch_deconv_init(void* D, const Geom& g, const double* gl_x, const double* gl_w,

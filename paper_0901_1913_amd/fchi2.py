@@ -19,9 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libfchi2.so")
 
 OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = range(6)
 FP64, MIXED = 0, 1
-KEEP_FOR_BACKWARD, GRAPH, FUSED_SPREAD = 1, 2, 4
+KEEP_FOR_BACKWARD, GRAPH, FUSED_SPREAD, WIDE_SOLVE = 1, 2, 4, 8
 NOALLOC_SCRATCH_BYTES = 64 << 20
-H_MAX = 8
+H_MAX = 16
+H_MAX_REGISTER = 8
 BIN_PIVOT, BIN_LOW_F, BIN_DC = 1, 2, 4
 CURVE_NONFINITE, CURVE_UNSORTED, CURVE_WRAP, CURVE_FEW, CURVE_EMPTY = 8, 16, 32, 64, 128
 
@@ -35,7 +36,7 @@ EXPORTS = (
     "fchi2_fine_scratch_bytes", "fchi2_fine_search",
     "fchi2_search_multi_workspace_bytes", "fchi2_search_multi", "fchi2_detrend",
     "fchi2_autotune_multi", "fchi2_search_generation", "fchi2_backward_at",
-    "fchi2_auto_n_freq", "fchi2_plan_n_freq", "fchi2_search_noalloc",
+    "fchi2_auto_n_freq", "fchi2_plan_n_freq", "fchi2_search_noalloc", "fchi2_search_coeffs",
 )
 PROF_STAGES = ("moments", "spread", "fft_first", "fft_mid", "fft_last", "solve",
                "bwd_solve", "bwd_fft", "bwd_gather", "bwd_final", "top_merge",
@@ -112,6 +113,8 @@ def lib() -> ctypes.CDLL:
     L.fchi2_total_points.restype = i64
     L.fchi2_search.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp, vp]
     L.fchi2_search.restype = ctypes.c_int
+    L.fchi2_search_coeffs.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp, vp, vp]
+    L.fchi2_search_coeffs.restype = ctypes.c_int
     L.fchi2_search_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.fchi2_search_noalloc.restype = ctypes.c_int
     L.fchi2_search_curves.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp, vp, vp, vp]
@@ -208,7 +211,7 @@ class Plan:
                  precision: str = "mixed", keep_for_backward: bool = False,
                  graph: bool = False, kernel_width: int = 0, curves_per_wave: int = 0,
                  first_bin: int = 0, oversampling: float = 0.0, t_span=None,
-                 fused_spread: bool = False, stream=None):
+                 fused_spread: bool = False, wide_solve: bool = False, stream=None):
         torch = _torch()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         if off.ndim != 1 or off.shape[0] < 2:
@@ -217,7 +220,7 @@ class Plan:
             raise ValueError("precision must be 'mixed' or 'fp64'")
         self._off = off
         flags = ((KEEP_FOR_BACKWARD if keep_for_backward else 0) | (GRAPH if graph else 0)
-                 | (FUSED_SPREAD if fused_spread else 0))
+                 | (FUSED_SPREAD if fused_spread else 0) | (WIDE_SOLVE if wide_solve else 0))
         desc = PlanDesc(
             n_curves=off.shape[0] - 1,
             offsets=off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -287,6 +290,26 @@ class Plan:
             if flags is not None else ctypes.c_void_p(0),
             ctypes.c_void_p(_stream_handle(stream))))
         return dchi2, chi2_0, flags
+
+    def search_coeffs(self, t, x, sigma, workspace=None, stream=None):
+        """Delta chi2, chi2_0, flags and the H model's coefficients
+        [n_curves, 2H+1, n_freq] (xbar added to A_0; basis in t - first time)."""
+        torch = _torch()
+        f64 = torch.float64
+        dev = t.device
+        nc, H, nf = self.n_curves, self.H, self.n_freq
+        dchi2 = torch.empty((nc, H, nf), dtype=self.out_dtype, device=dev)
+        chi2_0 = torch.empty(nc, dtype=f64, device=dev)
+        flags = torch.empty((nc, nf), dtype=torch.uint8, device=dev)
+        coef = torch.empty((nc, 2 * H + 1, nf), dtype=self.out_dtype, device=dev)
+        ws = self.workspace(dev) if workspace is None else workspace
+        _check(lib().fchi2_search_coeffs(
+            self._h, _dev_ptr(t, f64, self.n_total, "t"), _dev_ptr(x, f64, self.n_total, "x"),
+            _dev_ptr(sigma, f64, self.n_total, "sigma"), ctypes.c_void_p(ws.data_ptr()),
+            ctypes.c_size_t(ws.numel()), ctypes.c_void_p(dchi2.data_ptr()),
+            ctypes.c_void_p(chi2_0.data_ptr()), ctypes.c_void_p(flags.data_ptr()),
+            ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(_stream_handle(stream))))
+        return dchi2, chi2_0, flags, coef
 
     def search_noalloc(self, t, x, sigma, dchi2, chi2_0, flags=None, stream=None):
         """fchi2_search into caller outputs with the library's device scratch as

@@ -53,7 +53,6 @@ def _plan(**kw):
     (dict(f_max=0.0), F.ERR_ARG, "f_max"),
     (dict(f_max=float("nan")), F.ERR_ARG, "f_max"),
     (dict(precision=7), F.ERR_ARG, "precision"),
-    (dict(flags=64), F.ERR_ARG, "flag"),
     (dict(kernel_width=3), F.ERR_ARG, "kernel_width"),
     (dict(kernel_width=2), F.ERR_ARG, "kernel_width"),
     (dict(offsets=[1, 5]), F.ERR_ARG, "offsets[0]"),
@@ -63,6 +62,10 @@ def _plan(**kw):
     (dict(first_bin=2 ** 41), F.ERR_UNSUPPORTED, "first_bin"),
     (dict(first_bin=4096, flags=F.KEEP_FOR_BACKWARD), F.ERR_UNSUPPORTED, "no backward"),
     (dict(first_bin=4096, kernel_width=1), F.ERR_UNSUPPORTED, "no floor gridding"),
+    (dict(H=9, flags=F.KEEP_FOR_BACKWARD), F.ERR_UNSUPPORTED, "backward needs H <= 8"),
+    (dict(H=3, flags=F.KEEP_FOR_BACKWARD | F.WIDE_SOLVE), F.ERR_UNSUPPORTED, "backward needs"),
+    (dict(H=12, first_bin=4096), F.ERR_UNSUPPORTED, "band plans need H <= 8"),
+    (dict(flags=16), F.ERR_ARG, "flag"),
 ])
 def test_plan_argument_errors(kw, code, frag):
     st, msg = _plan(**kw)
