@@ -1,15 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the F-chi2 hot path on one MI355X.
 
-A step is one fchi2_search over the whole workload (moments, spreading, FFT
-passes, per-bin assembly and Cholesky for every H'), with the inputs already
-resident in device memory.  The value is trial frequencies x H per second.
+The headline is the batched survey: one step is one fchi2_search over all
+10^4 curves of the batch workload (moments, spreading, FFT passes, per-bin
+assembly and Cholesky for every H'), replayed from a HIP graph, with the
+inputs already resident in device memory; the value is trial frequencies x H
+per second.  The same search run as a loop of single-curve calls (the plain
+form, same kernels) is timed beside it.
 
-Prints one JSON line.  Beside the throughput it reports, for the kernel that
-takes the most time, its algorithmic bytes per launch divided by its average
-launch time (HIP events recorded by the library on the search stream during
-the timed steps), and the FP64 CPU oracle timed on a bounded sample of bins of
-the same workload (whose values double as a parity spot check).
+Prints one JSON line.  Beside the throughput it reports the roofline of the
+kernel that takes the most time (algorithmic bytes by the scope table's byte
+model per launch, over its average launch duration measured with HIP events
+on the search stream in a separate profiled pass), the same model for the
+gridding + FFT stages and for the whole step, the FP64 solve rate, the FP64
+CPU oracle timed on a bounded sample of the batch (whose values double as a
+parity check), and one line per other workload (plain FP64, long curve,
+differentiation, precision stress in mixed and FP64).
 """
 from __future__ import annotations
 
@@ -25,16 +31,106 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 METRIC = ("trial freqs·H/sec for Δχ² (rel err ≤1e-5 vs FP64 oracle); "
           "batched vs plain")
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch from the committed PMC summary, per stage, or None
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def sec8d_bytes(n, H, n_freq, b, o):
+    """Algorithmic bytes per curve, by the scope table's model for the
+    HBM-grid schedule (3H real grids of L = 4 n_freq cells of b bytes, a
+    two-pass FFT with an output-pruned last pass, o-byte outputs):
+    inputs 24 n; spreading writes L; FFT pass 1 reads and writes L; the last
+    pass reads L and writes 2 n_freq; the assembly reads 2 n_freq; output
+    H n_freq o.  A full read + write pass of the grids is 2 L per grid."""
+    L = 4 * n_freq
+    g = 3 * H * b
+    return {"inputs": 24 * n, "spread": g * L, "full_pass": g * 2 * L,
+            "last_pass": g * (L + 2 * n_freq), "solve": g * 2 * n_freq + H * n_freq * o,
+            "gridding_fft": 24 * n + g * (4 * L + 2 * n_freq),
+            "step": 24 * n + g * (4 * L + 4 * n_freq) + H * n_freq * o}
+
+
+def solve_flops(H):
+    """FP64 flops per bin of assembly + prefix Cholesky (scope table):
+    d^3/3 + 2 d^2 + d (d + 1), d = 2H + 1."""
+    d = 2 * H + 1
+    return d ** 3 / 3 + 2 * d * d + d * (d + 1)
+
+
+def stage_roofline(cur, stages, steps_profiled, b, o, schedule):
+    """Per-stage bytes by the scope table's model and rates from a profiled
+    pass: the dominant kernel's roofline, the gridding + FFT and whole-step
+    effective bandwidths, and the solve's FP64 rate.  Each FFT pass is a full
+    read and write of the grids (a schedule with more than two passes moves
+    more than the two-pass model counts); with the spreading fused into the
+    first pass, that pass is also charged the spreading's grid write."""
+    H, nf, nc = cur.H, cur.n_freq, cur.n_curves
+    n_tot = int(cur.t.shape[0])
+    m = sec8d_bytes(n_tot / nc, H, nf, b, o)
+    n_pass = len(schedule["fft_log_radices"])
+    per_stage_bytes = {  # per search, all curves
+        "spread": nc * (m["spread"]) + 24 * n_tot,
+        "fft_first": nc * m["full_pass"], "fft_mid": nc * m["full_pass"] * max(0, n_pass - 2),
+        "fft_last": nc * m["last_pass"], "solve": nc * m["solve"]}
+    if schedule.get("fused_spread"):
+        per_stage_bytes["fft_first"] += nc * m["spread"]
+        per_stage_bytes["spread"] = 24 * n_tot
+    ms = {k: v[0] / steps_profiled for k, v in stages.items() if v[1]}
+    launches = {k: v[1] / steps_profiled for k, v in stages.items() if v[1]}
+    cand = {k: ms[k] for k in per_stage_bytes if k in ms}
+    dom = max(cand, key=cand.get)
+    avg_launch_ms = ms[dom] / launches[dom]
+    bytes_launch = per_stage_bytes[dom] / launches[dom]
+    achieved = bytes_launch / (avg_launch_ms * 1e-3) / 1e9
+    fft_ms = sum(ms.get(k, 0.0) for k in ("spread", "fft_first", "fft_mid", "fft_last"))
+    step_ms = sum(ms.values())
+    grid_gb = nc * m["gridding_fft"] / 1e9
+    step_gb = nc * m["step"] / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "bytes_per_launch": int(bytes_launch),
+            "avg_launch_ms": round(avg_launch_ms, 5), "launches_per_step": launches[dom],
+            "byte_model": "3H real grids x b bytes: a full pass reads and writes 2 L per grid"}
+    sections = {
+        "gridding_fft": {"gb_per_step_sec8d": round(grid_gb, 2), "ms": round(fft_ms, 4),
+                         "gbs": round(grid_gb / (fft_ms * 1e-3), 1),
+                         "frac": round(grid_gb / (fft_ms * 1e-3) / HBM_PEAK_GBS, 4)},
+        "whole_step": {"gb_per_step_sec8d": round(step_gb, 2), "ms": round(step_ms, 4),
+                       "gbs": round(step_gb / (step_ms * 1e-3), 1),
+                       "frac": round(step_gb / (step_ms * 1e-3) / HBM_PEAK_GBS, 4)},
+    }
+    if "solve" in ms:
+        fl = solve_flops(H) * nf * nc
+        tf = fl / (ms["solve"] * 1e-3) / 1e12
+        sections["solve_fp64"] = {"tflops": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
+                                  "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                                  "flops_per_bin": round(solve_flops(H), 1)}
+    stage_ms = {k: round(v, 5) for k, v in ms.items()}
+    return roof, sections, stage_ms
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of each stage from a committed rocprofv3 PMC
+    summary (profiles/<name>_hbm_traffic.md), or {} if there is none, or None
     for a stage whose kernel source changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"{workload}_mixed_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.md")
     if not os.path.exists(path):
         return {}
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
@@ -48,152 +144,178 @@ def measured_traffic(workload):
         h = hashlib.sha256()
         ok = st in src
         for f in src.get(st, []):
-            path = os.path.join(ROOT, "paper_0901_1913_amd", "csrc", f)
-            if not os.path.isfile(path):
+            fp = os.path.join(ROOT, "paper_0901_1913_amd", "csrc", f)
+            if not os.path.isfile(fp):
                 ok = False
                 break
-            h.update(open(path, "rb").read())
+            h.update(open(fp, "rb").read())
         ok = ok and h.hexdigest()[:16] == meta.get("source_sha256_16", {}).get(st)
         out[st] = int(nbytes) if ok else None
     return out
 
 
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def pair_extents(cur, w):
-    """Nonzero cells of each packed grid (weight pairs, then data pairs)."""
-    H, nf = cur.H, cur.n_freq
-    L = 4 * nf
-    df = cur.f_max / nf
-    span = float(cur.t[-1] - cur.t[0])
-    c_off = w // 2 + 2
-    ms = [2 * p + 2 for p in range(H)] + [min(2 * j + 2, H) for j in range((H + 1) // 2)]
-    return [min(L, int((m * (span * df)) * L + c_off) + w // 2 + 1) for m in ms]
-
-
-def stage_bytes(cur, elem, out_elem, w):
-    """Algorithmic HBM bytes per launch of each forward stage (one curve)."""
-    H, nf = cur.H, cur.n_freq
-    L = 4 * nf
-    P = H + (H + 1) // 2
-    E = pair_extents(cur, w)
-    n = cur.t.shape[0]
-    return {
-        "moments": 24 * n,
-        "spread": 24 * n + sum(E) * elem,
-        "fft_first": sum(E) * elem + P * L * elem,
-        "fft_mid": 2 * P * L * elem,
-        "fft_last": P * L * elem + P * 2 * nf * elem,
-        "solve": P * 2 * nf * elem + nf * elem + H * nf * out_elem + nf,
-    }
-
-
-def _oracle_chunk(args):
+def _oracle_task(args):
     t, x, s, freqs, H = args
     from threadpoolctl import threadpool_limits
     from oracle import fchi2_oracle as ora
     with threadpool_limits(1):
         r = ora.dchi2(t, x, s, freqs, H)
-    return r["dchi2"], r["kappa"]
+    return r["dchi2"], r["kappa"], r["span"]
 
 
-def cpu_baseline(cur, budget_s, seed=7):
-    """Time the oracle on a seeded bin sample sized to ~budget_s of CPU work."""
+def pool_size():
+    """Worker processes for the oracle: the CPUs this process may run on,
+    capped at 16 (the host CPU share that goes with one GPU on the benchmark
+    machines, whatever the host reports in all)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_pool(tasks):
+    """Run oracle tasks on pool_size() processes; returns the results, the
+    wall time and the number of processes."""
     import multiprocessing as mp
-    cores = max(1, min(16, os.cpu_count() or 1))
-    t, x, s = cur.curve(0)
+    cores = pool_size()
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_task, tasks, chunksize=1)
+    return res, time.perf_counter() - t0, cores
+
+
+def batch_sample(cur, seed=7, n_strat=32, bins_strat=96, bins_each=3):
+    """The bounded oracle sample of the batch: 32 curves stratified by length
+    and by signal / noise (8 length quartile x signal classes, 4 curves each)
+    with bins_strat seeded random bins each, plus bins_each random bins on
+    every curve.  Returns {curve: sorted bins}."""
     rng = np.random.default_rng(seed)
-    nf = cur.n_freq
-    # Probe the cost of one bin on one core.
-    probe = np.array([nf // 3], dtype=np.int64)
-    t0 = time.perf_counter()
-    _oracle_chunk((t, x, s, probe * (cur.f_max / nf), cur.H))
-    per_bin = max(time.perf_counter() - t0, 1e-4)
-    # One core on its own: a short run of consecutive bins in this process.
-    one = np.arange(1, 33, dtype=np.int64) * (nf // 64)
-    t0 = time.perf_counter()
-    _oracle_chunk((t, x, s, one * (cur.f_max / nf), cur.H))
-    one_core = len(one) * cur.H / (time.perf_counter() - t0)
-    n_bins = int(max(cores, min(4096, budget_s * cores / per_bin)))
-    n_bins = (n_bins // cores) * cores
-    bins = np.sort(rng.choice(np.arange(1, nf), size=n_bins, replace=False))
-    chunks = np.array_split(bins, cores)
-    ctx = mp.get_context("fork")
-    t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        parts = pool.map(_oracle_chunk, [(t, x, s, c * (cur.f_max / nf), cur.H) for c in chunks])
-    el = time.perf_counter() - t0
-    return (bins, np.concatenate([p[0] for p in parts], axis=1),
-            np.concatenate([p[1] for p in parts]), el, cores, one_core)
+    nc = cur.n_curves
+    n = np.diff(cur.offsets)
+    sig = np.asarray(cur.meta.get("with_signal", np.zeros(nc, dtype=bool)), dtype=bool)
+    q = np.searchsorted(np.quantile(n, [0.25, 0.5, 0.75]), n, side="right")
+    pick = []
+    for qq in range(4):
+        for ss in (False, True):
+            idx = np.nonzero((q == qq) & (sig == ss))[0]
+            pick += list(rng.choice(idx, size=min(n_strat // 8, len(idx)), replace=False))
+    sample = {}
+    for c in range(nc):
+        sample[c] = set(rng.choice(np.arange(1, cur.n_freq), size=bins_each, replace=False))
+    for c in pick:
+        sample[int(c)] |= set(rng.choice(np.arange(1, cur.n_freq), size=bins_strat,
+                                         replace=False))
+    return {c: np.array(sorted(b), dtype=np.int64) for c, b in sample.items()}, \
+        [int(c) for c in pick]
 
 
-def batched_vs_plain(steps):
-    """The batch workload as one graph-replayed search vs a loop of single-curve searches."""
+def parity_summary(errs, gates):
+    e = np.concatenate([x[:, g].ravel() for x, g in zip(errs, gates)])
+    a = np.concatenate([x.ravel() for x in errs])
+    return {"gated_values": int(e.size), "max_rel_err_gated": float(e.max()) if e.size else None,
+            "median_rel_err_gated": float(np.median(e)) if e.size else None,
+            "max_rel_err_all": float(a.max())}
+
+
+def time_search(plan, t, x, s, steps, warmup, stream, **kw):
+    """Median-free mean over `steps` searches after `warmup`, HIP events on
+    the search stream, no per-launch events inside the timed region."""
+    import torch
+    d = kw.pop("dchi2")
+    for _ in range(warmup):
+        plan.search(t, x, s, dchi2=d, stream=stream, **kw)
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.search(t, x, s, dchi2=d, stream=stream, **kw)
+    e1.record(stream)
+    stream.synchronize()
+    wall = time.perf_counter() - w0
+    return e0.elapsed_time(e1) / steps, 1e3 * wall / steps
+
+
+def profiled_pass(plan, t, x, s, stream, reps=1, **kw):
+    """Per-stage launch times from the library's event pairs (graph replay is
+    bypassed while profiling): {stage: (total ms, launches)} over reps."""
+    plan.profile(True)
+    for _ in range(reps):
+        plan.search(t, x, s, stream=stream, **kw)
+    stream.synchronize()
+    st = plan.profile_read()
+    plan.profile(False)
+    return st
+
+
+_ORACLE_CACHE = {}
+
+
+def workload_line(name, steps, warmup, precision=None, parity_bins=256, seed=11,
+                  extra_bins=None):
+    """Timing (autotuned), stage split, roofline and oracle parity on sampled
+    bins of one single-curve workload."""
     import torch
     from paper_0901_1913_amd import fchi2 as F
     from paper_0901_1913_amd import synth
-    cur = synth.make("batch")
-    log(f"batch: {cur.n_curves} curves, {cur.t.shape[0]} points, H={cur.H}, "
-        f"n_freq={cur.n_freq}")
+    cur = synth.make(name) if precision is None else synth.make(name, precision=precision)
+    prec = cur.precision
     t = torch.from_numpy(cur.t).cuda()
     x = torch.from_numpy(cur.x).cuda()
     s = torch.from_numpy(cur.sigma).cuda()
-    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision,
-                  graph=True)
+    # Graph replay (one launch call per search) on a stream of its own, as for
+    # the batch: a small search is otherwise limited by the host's calls.
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=prec, graph=True)
     ws = plan.workspace()
+    t0 = time.perf_counter()
     schedule = plan.autotune(t, x, s)
-    log(f"batch autotuned: {schedule}")
-    dchi2 = torch.empty((cur.n_curves, cur.H, cur.n_freq), dtype=plan.out_dtype, device="cuda")
-    chi2_0 = torch.empty(cur.n_curves, dtype=torch.float64, device="cuda")
+    tune_s = time.perf_counter() - t0
+    d = torch.empty((1, cur.H, cur.n_freq), dtype=plan.out_dtype, device="cuda")
+    c0 = torch.empty(1, dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
-    units = cur.n_curves * cur.n_freq * cur.H
     with torch.cuda.stream(stream):
-        plan.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, workspace=ws, want_flags=False)
-        stream.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            plan.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, workspace=ws, want_flags=False)
-        e1.record(stream)
-        stream.synchronize()
-        ms_b = e0.elapsed_time(e1) / steps
-        ref = dchi2.clone()
-        log(f"batched: {ms_b:.3f} ms/step")
-        # Plain form: the same kernels, one curve per call, no graph.
-        e0.record(stream)
-        for c in range(cur.n_curves):
-            plan.search_curves(c, 1, t, x, s, dchi2, chi2_0, workspace=ws, stream=stream)
-        e1.record(stream)
-        stream.synchronize()
-        ms_p = e0.elapsed_time(e1)
-        same = bool(torch.equal(ref, dchi2))
-        log(f"plain loop: {ms_p:.3f} ms per pass (results identical: {same})")
-        del ref, dchi2
-        # Significance epilogue: K candidates per curve instead of the rows.
-        K = 16
-        plan.search_top(t, x, s, K=K, stream=stream)
-        e0.record(stream)
-        for _ in range(steps):
-            top = plan.search_top(t, x, s, K=K, stream=stream)
-        e1.record(stream)
-        stream.synchronize()
-        ms_top = e0.elapsed_time(e1) / steps
-        log(f"fused top-{K}: {ms_top:.3f} ms/step")
+        ms, wall = time_search(plan, t, x, s, steps, warmup, stream, dchi2=d, chi2_0=c0,
+                               workspace=ws, want_flags=False)
+        st = profiled_pass(plan, t, x, s, stream, reps=2, dchi2=d, chi2_0=c0, workspace=ws,
+                           want_flags=False)
+    b, o = (4, 4) if prec == "mixed" else (8, 8)
+    roof, sections, stage_ms = stage_roofline(cur, st, 2, b, o, schedule)
+    units = cur.n_freq * cur.H
+    # Parity on seeded bins (plus the caller's bins), oracle on all cores.
+    rng = np.random.default_rng(seed)
+    bins = rng.choice(np.arange(1, cur.n_freq), size=parity_bins, replace=False)
+    if extra_bins is not None:
+        bins = np.concatenate([bins, extra_bins])
+    bins = np.unique(bins[(bins >= 1) & (bins < cur.n_freq)])
+    dd = d.double().cpu().numpy()[0][:, bins]
     plan.close()
-    torch.cuda.synchronize()
-    return {"workload": "batch", "n_curves": cur.n_curves, "n_total": int(cur.t.shape[0]),
-            "H": cur.H, "n_freq": cur.n_freq, "precision": cur.precision,
-            "batched_value": round(units / (ms_b * 1e-3), 1), "batched_ms_per_step": round(ms_b, 4),
-            "plain_value": round(units / (ms_p * 1e-3), 1), "plain_ms_per_pass": round(ms_p, 3),
-            "speedup": round(ms_p / ms_b, 3), "identical_outputs": same,
-            "schedule": schedule, "unit": "freq*H/s",
-            "fused_top16_value": round(units / (ms_top * 1e-3), 1),
-            "fused_top16_ms_per_step": round(ms_top, 4),
-            "rows_bytes": int(cur.n_curves * cur.H * cur.n_freq * 4),
-            "top16_bytes": int(sum(v.numel() * v.element_size() for v in top.values()))}
+    key = (name, bins.tobytes())
+    if key not in _ORACLE_CACHE:
+        chunks = np.array_split(bins, max(1, min(len(bins), 4 * pool_size())))
+        _ORACLE_CACHE[key] = oracle_pool([(cur.t, cur.x, cur.sigma,
+                                           c * (cur.f_max / cur.n_freq), cur.H)
+                                          for c in chunks if len(c)])
+    res, el, cores = _ORACLE_CACHE[key]
+    d_ora = np.concatenate([r[0] for r in res], axis=1)
+    kappa = np.concatenate([r[1] for r in res])
+    span = res[0][2]
+    from oracle import fchi2_oracle as ora
+    err = ora.rel_err(dd, d_ora)
+    kmax = 1e2 if prec == "mixed" else 1e6
+    fr = bins * (cur.f_max / cur.n_freq)
+    gate = (fr >= 1.0 / span) & (kappa <= kmax)
+    par = parity_summary([err], [gate])
+    par.update({"bins": int(len(bins)), "gate": f"k >= 1, f >= 1/span, kappa <= {kmax:g}"})
+    log(f"{name} {prec}: {ms:.4f} ms/search, parity max {par['max_rel_err_gated']:.3e}")
+    return {"workload": name, "n": int(cur.t.shape[0]), "H": cur.H, "n_freq": cur.n_freq,
+            "f_max": cur.f_max, "precision": prec, "ms_per_search": round(ms, 5),
+            "wall_ms_per_search": round(wall, 5), "value": round(units / (ms * 1e-3), 1),
+            "unit": "freq*H/s", "schedule": schedule, "autotune_s": round(tune_s, 2),
+            "stages_ms": stage_ms, "roofline": roof, "sections": sections, "parity": par,
+            "oracle": {"value": round(len(bins) * cur.H / el, 2), "cores": cores,
+                       "bins": int(len(bins)), "wall_s": round(el, 2)}}
 
 
 def multi_vs_curves(steps):
@@ -386,23 +508,17 @@ def band_share_timing(steps, G=8):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="long",
-                    choices=["plain", "long", "diff", "stress"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the batched-survey vs plain-loop comparison")
-    ap.add_argument("--batched-steps", type=int, default=5)
-    ap.add_argument("--no-multi", action="store_true",
-                    help="skip the shared-alpha multi-source comparison")
-    ap.add_argument("--no-variants", action="store_true",
-                    help="skip the floor-gridding and detrending timings")
-    ap.add_argument("--no-gradient", action="store_true",
-                    help="skip the adjoint timing on the diff workload")
-    ap.add_argument("--no-band", action="store_true",
-                    help="skip the frequency-band share of the stress curve")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the single-curve loop beside the batched search")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the plain, long, diff and stress lines")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the shared-alpha, variants and band-share sections")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file for the batched search")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device copy of this many MiB (a known-size kernel "
                          "against which HBM counters are scaled)")
@@ -423,23 +539,21 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
-    cur = synth.make(a.workload)
-    log(f"workload {a.workload}: n={cur.t.shape[0]} H={cur.H} n_freq={cur.n_freq} "
-        f"precision={cur.precision}")
-    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision)
+    cur = synth.make("batch")
+    n_tot = int(cur.t.shape[0])
+    log(f"batch: {cur.n_curves} curves, {n_tot} points, H={cur.H}, n_freq={cur.n_freq}")
     t = torch.from_numpy(cur.t).cuda()
     x = torch.from_numpy(cur.x).cuda()
     s = torch.from_numpy(cur.sigma).cuda()
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision,
+                  graph=True)
     ws = plan.workspace()
     t0 = time.perf_counter()
-    schedule = plan.autotune(t, x, s)
+    schedule = plan.autotune(t, x, s, cache_path=a.tune_cache)
     torch.cuda.synchronize()
-    log(f"autotuned in {time.perf_counter() - t0:.2f} s (not timed): {schedule}")
-    dchi2 = torch.empty((1, cur.H, cur.n_freq), dtype=plan.out_dtype, device="cuda")
-    chi2_0 = torch.empty(1, dtype=torch.float64, device="cuda")
-    flags = torch.empty((1, cur.n_freq), dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
-
+    log(f"batch autotuned in {time.perf_counter() - t0:.1f} s (not timed): {schedule}")
+    dchi2 = torch.empty((cur.n_curves, cur.H, cur.n_freq), dtype=plan.out_dtype, device="cuda")
+    chi2_0 = torch.empty(cur.n_curves, dtype=torch.float64, device="cuda")
     if a.calib_copy_mb > 0:
         nel = a.calib_copy_mb * (1 << 20) // 4
         c_src = torch.ones(nel, dtype=torch.float32, device="cuda")
@@ -449,128 +563,123 @@ def main(argv=None):
         torch.cuda.synchronize()
         log(f"calibration copy: {a.calib_copy_mb} MiB read + {a.calib_copy_mb} MiB written")
         del c_src, c_dst
-    for _ in range(a.warmup):
-        plan.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, flags=flags, workspace=ws)
-    torch.cuda.synchronize()
-    log(f"warmup done ({a.warmup})")
-
-    plan.profile(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(a.steps):
-        plan.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, flags=flags, workspace=ws)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_step = ev0.elapsed_time(ev1) / a.steps
-    stages = plan.profile_read()
-    plan.profile(False)
-    log(f"timed {a.steps} steps: {ms_step:.4f} ms/step (wall {1e3 * wall / a.steps:.4f})")
-
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
     units = cur.n_curves * cur.n_freq * cur.H
-    value = units / (ms_step * 1e-3)
-    w = plan.info()["kernel_width"]
-    elem = 8 if cur.precision == "mixed" else 16
-    out_elem = 4 if cur.precision == "mixed" else 8
-    nbytes = stage_bytes(cur, elem, out_elem, w)
-    st_avg = {k: (v[0] / v[1] if v[1] else 0.0, v[1] // a.steps) for k, v in stages.items()
-              if v[1]}
-    per_step = {k: round(v[0] * v[1], 5) for k, v in st_avg.items()}
-    dom = max(per_step, key=per_step.get)
-    dom_ms = st_avg[dom][0]
-    achieved = nbytes[dom] / (dom_ms * 1e-3) / 1e9
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (measured_traffic(a.workload).get(dom)
-                        if cur.precision == "mixed" else None),
-            "bytes_per_launch": int(nbytes[dom]),
-            "avg_launch_ms": round(dom_ms, 5)}
-    stage_gbs = {k: round(nbytes[k] / (v[0] * 1e-3) / 1e9, 1) for k, v in st_avg.items()
-                 if k in nbytes and v[0] > 0}
-
-    # Significance epilogue on the same plan: K candidates instead of the rows.
-    K = 16
-    top = plan.search_top(t, x, s, K=K)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(a.steps):
-        top = plan.search_top(t, x, s, K=K)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_top = ev0.elapsed_time(ev1) / a.steps
-    log(f"fused top-{K}: {ms_top:.4f} ms/step")
-    signif = {"K": K, "ms_per_step": round(ms_top, 5), "value": round(units / (ms_top * 1e-3), 1),
-              "best_bins": top["idx"][0, :4].tolist(),
-              "best_log_p": [round(v, 3) for v in top["log_p"][0, :4].tolist()]}
-    # Fine search on the ungridded points around those K candidates (R trials
-    # over +-1 bin, three zoom levels), FP64 direct sums.
-    R = 64
-    fc = torch.where(top["idx"] >= 0, top["idx"].double() * (cur.f_max / cur.n_freq),
-                     torch.full_like(top["log_p"], float("nan")))
-    fine = plan.refine(t, x, s, fc, levels=3, R=R)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(a.steps):
-        fine = plan.refine(t, x, s, fc, levels=3, R=R)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_fine = ev0.elapsed_time(ev1) / a.steps
-    pairs = 3 * K * R * int(cur.t.shape[0])
-    log(f"fine search, 3 levels x {K} x {R}: {ms_fine:.4f} ms")
-    signif["fine"] = {"levels": 3, "R": R, "ms": round(ms_fine, 5),
-                      "point_trials_per_s": round(pairs / (ms_fine * 1e-3), 1),
-                      "f_best": [round(v, 9) for v in fine["f_best"][0, :4].tolist()]}
-
-    d_gpu = dchi2.double().cpu().numpy()[0]
+    with torch.cuda.stream(stream):
+        ms_step, wall_ms = time_search(plan, t, x, s, a.steps, a.warmup, stream, dchi2=dchi2,
+                                       chi2_0=chi2_0, workspace=ws, want_flags=False)
+        log(f"batched (graph replay): {ms_step:.3f} ms/step over {a.steps} steps "
+            f"(wall {wall_ms:.3f})")
+        ref = dchi2.clone()
+        st = profiled_pass(plan, t, x, s, stream, dchi2=dchi2, chi2_0=chi2_0, workspace=ws,
+                           want_flags=False)
+        ms_plain, same = None, None
+        if not a.no_plain:
+            # Plain form: the same kernels and schedule, one curve per call, no graph.
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for c in range(cur.n_curves):
+                plan.search_curves(c, 1, t, x, s, dchi2, chi2_0, workspace=ws, stream=stream)
+            e1.record(stream)
+            stream.synchronize()
+            ms_plain = e0.elapsed_time(e1)
+            same = bool(torch.equal(ref, dchi2))
+            log(f"plain loop: {ms_plain:.3f} ms per pass (identical outputs: {same})")
+        # Significance epilogue: K candidates per curve instead of the rows.
+        K = 16
+        plan.search_top(t, x, s, K=K, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            top = plan.search_top(t, x, s, K=K, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+        ms_top = e0.elapsed_time(e1) / a.steps
+        log(f"fused top-{K}: {ms_top:.3f} ms/step")
+    roof, sections, stage_ms = stage_roofline(cur, st, 1, 4, 4, schedule)
+    roof["traffic"] = measured_traffic("batch").get(roof["kernel"])
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "freq*H/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 5),
+        "metric": METRIC, "value": round(units / (ms_step * 1e-3), 1), "unit": "freq*H/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if cur.precision == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": a.workload, "n": int(cur.t.shape[0]), "H": cur.H,
-                   "n_freq": cur.n_freq, "f_max": cur.f_max, "precision": cur.precision,
-                   "schedule": plan.info()},
-        "roofline": roof,
-        "stages_ms_per_step": per_step,
-        "stages_gbs": stage_gbs,
-        "significance": signif,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "batch", "n_curves": cur.n_curves, "n_total": n_tot,
+                   "H": cur.H, "n_freq": cur.n_freq, "f_max": cur.f_max,
+                   "precision": cur.precision, "form": "one graph-replayed search",
+                   "schedule": schedule},
+        "roofline": roof, "sections": sections, "stages_ms_per_step": stage_ms,
+        "plain": None if ms_plain is None else {
+            "ms_per_pass": round(ms_plain, 3), "value": round(units / (ms_plain * 1e-3), 1),
+            "speedup_batched_over_plain": round(ms_plain / ms_step, 3),
+            "identical_outputs": same},
+        "fused_top16": {"ms_per_step": round(ms_top, 4),
+                        "value": round(units / (ms_top * 1e-3), 1),
+                        "rows_bytes": int(cur.n_curves * cur.H * cur.n_freq * 4),
+                        "top16_bytes": int(sum(v.numel() * v.element_size()
+                                               for v in top.values()))},
     }
+    # Oracle on a bounded, stratified sample of the batch: CPU baseline and parity.
     if not a.no_cpu_baseline:
         from oracle import fchi2_oracle as ora
-        log("oracle CPU baseline ...")
-        bins, d_ora, kappa, el, cores, one_core = cpu_baseline(cur, a.cpu_seconds)
-        v_cpu = len(bins) * cur.H / el
+        sample, strat = batch_sample(cur)
+        tasks, order = [], []
+        df = cur.f_max / cur.n_freq
+        for c, bins in sample.items():
+            tt, xx, ss = cur.curve(c)
+            # the stratified curves' bins split across tasks to balance the pool
+            for part in np.array_split(bins, max(1, len(bins) // 16)):
+                tasks.append((tt, xx, ss, part * df, cur.H))
+                order.append((c, part))
+        log(f"oracle CPU baseline: {sum(len(b) for b in sample.values())} bins on "
+            f"{cur.n_curves} curves ({len(strat)} stratified) ...")
+        res, el, cores = oracle_pool(tasks)
+        dd = ref.float().cpu().numpy() if ref.dtype != torch.float64 else ref.cpu().numpy()
+        errs, gates = [], []
+        for (c, part), (d_ora, kappa, span) in zip(order, res):
+            e = ora.rel_err(dd[c][:, part].astype(np.float64), d_ora)
+            fr = part * df
+            errs.append(e)
+            gates.append((fr >= 1.0 / span) & (kappa <= 1e2) if span > 0 else kappa <= 1e2)
+        nb = sum(len(p) for _, p in order)
+        v_cpu = nb * cur.H / el
+        # one core: a short in-process run on a stratified curve
+        c1 = strat[0]
+        b1 = sample[c1][:24]
+        t1 = time.perf_counter()
+        _oracle_task((*cur.curve(c1), b1 * df, cur.H))
+        one = len(b1) * cur.H / (time.perf_counter() - t1)
         out["cpu_baseline"] = {
-            "value": round(v_cpu, 2), "unit": "freq*H/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{len(bins)} seeded random bins of the {a.workload} workload "
-                      f"(all H'=1..{cur.H}), {el:.1f} s wall",
-            "one_core_value": round(one_core, 2),
-            "full_grid_s_extrapolated": round(units / v_cpu, 1)}
-        span = float(cur.t[-1] - cur.t[0])
-        freqs = bins * (cur.f_max / cur.n_freq)
-        err = ora.rel_err(d_gpu[:, bins], d_ora)
-        kmax = 1e2 if cur.precision == "mixed" else 1e6
-        ok = (freqs >= 1.0 / span) & (kappa <= kmax)
-        out["parity"] = {"bins": int(len(bins)), "gated_bins": int(ok.sum()),
-                         "gate": f"f >= 1/span, kappa <= {kmax:g}",
-                         "max_rel_err_gated": float(err[:, ok].max()) if ok.any() else None,
-                         "median_rel_err_gated": float(np.median(err[:, ok])) if ok.any() else None,
-                         "max_rel_err_all": float(err.max())}
+            "value": round(v_cpu, 2), "unit": "freq*H/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{nb} bins (all H'=1..{cur.H}) of the batch workload: {len(strat)} "
+                       f"curves stratified by length quartile and signal/noise with 96 "
+                       f"seeded bins each, plus 3 seeded bins on every curve; "
+                       f"{el:.1f} s wall"),
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "one_core_value": round(one, 2),
+            "full_search_s_extrapolated": round(units / v_cpu, 1)}
+        out["parity"] = parity_summary(errs, gates)
+        out["parity"].update({"bins": nb, "gate": "k >= 1, f >= 1/span, kappa <= 100"})
+        log(f"batch parity: max gated {out['parity']['max_rel_err_gated']:.3e}")
     plan.close()
-    del dchi2, ws
-    if not a.no_batched:
-        out["batched"] = batched_vs_plain(a.batched_steps)
-    if not a.no_multi:
-        out["multi"] = multi_vs_curves(a.batched_steps)
-    if not a.no_gradient:
-        out["gradient"] = gradient_timing(a.steps)
-    if not a.no_variants:
+    del dchi2, ref, ws
+    torch.cuda.empty_cache()
+    if not a.no_workloads:
+        wl = {}
+        k0 = int(round(2 ** 14 / 10.0 / 2.37))
+        wl["plain_fp64"] = workload_line("plain", a.steps, a.warmup,
+                                         extra_bins=np.arange(k0 - 4, k0 + 5))
+        wl["long_mixed"] = workload_line("long", a.steps, a.warmup)
+        wl["diff"] = gradient_timing(a.steps)
+        wl["stress_mixed"] = workload_line("stress", max(3, a.steps // 2), 2, parity_bins=192)
+        torch.cuda.empty_cache()
+        wl["stress_fp64"] = workload_line("stress", max(3, a.steps // 2), 2, precision="fp64",
+                                          parity_bins=192)
+        out["workloads"] = wl
+    if not a.no_extras:
+        torch.cuda.empty_cache()
+        out["multi"] = multi_vs_curves(max(3, a.steps // 2))
         out["variants"] = variants_timing(a.steps)
-    if not a.no_band:
         out["band_share"] = band_share_timing(a.steps)
     print(json.dumps(out), flush=True)
     return 0

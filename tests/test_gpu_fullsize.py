@@ -1,10 +1,13 @@
 """Parity at the full workload sizes, on bins the oracle evaluates one by one.
 
 Each test runs the search as bench.py does (default plan for the workload,
-autotuned before the search) and compares seeded samples of bins, plus the neighbourhood of the
-injected signal, with the FP64 oracle under the gate of the target
-(rel err <= 1e-5 on bins with k >= 1, f >= 1/span, kappa <= 1e2 mixed /
-1e6 FP64).
+autotuned before the search) and compares samples of bins with the FP64
+oracle under the gate of the target (rel err <= 1e-5 on bins with k >= 1,
+f >= 1/span, kappa <= 1e2 mixed / 1e6 FP64): seeded random bins, the
+neighbourhood of the injected signal, the 32 highest local maxima of the
+H row +-2 bins, and the 32 lowest bins of the gate (f just above 1/span); for
+the batch, 32 curves stratified by length and by signal / noise plus 16 bins
+on every curve.  The oracle runs on the host's CPU share in parallel.
 """
 import numpy as np
 import pytest
@@ -12,6 +15,7 @@ import pytest
 from oracle import fchi2_oracle as ora
 from paper_0901_1913_amd import fchi2 as F
 from paper_0901_1913_amd import synth
+from tests import oracle_pool
 from tests.gpu_util import note, run_search, sample_bins, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -70,14 +74,51 @@ def test_diff_full_size_forward_and_gradient():
     e, _ = _compare(cur, d, bins, "mixed", label="diff full")
     assert e.max() <= 1e-5
     rx, rs = ora.grad(cur.t, cur.x, cur.sigma, [(float(k) * df, cur.H, 1.0) for k in idx])
-    ex = np.linalg.norm(gx.cpu().numpy() - rx) / np.linalg.norm(rx)
-    es = np.linalg.norm(gs.cpu().numpy() - rs) / np.linalg.norm(rs)
-    print(f"diff full gradient: rel l2 dx {ex:.3e}, dsigma {es:.3e}", flush=True)
+    gx, gs = gx.cpu().numpy(), gs.cpu().numpy()
+    ex = np.linalg.norm(gx - rx) / np.linalg.norm(rx)
+    es = np.linalg.norm(gs - rs) / np.linalg.norm(rs)
+    # Element-wise too, so an error concentrated on a few points cannot hide
+    # in the norm: max |g - g_ora| / max |g_ora|.
+    mx = np.abs(gx - rx).max() / np.abs(rx).max()
+    ms = np.abs(gs - rs).max() / np.abs(rs).max()
+    print(f"diff full gradient: rel l2 dx {ex:.3e}, dsigma {es:.3e}; element-wise "
+          f"max dx {mx:.3e}, dsigma {ms:.3e}", flush=True)
     assert ex <= 1e-5 and es <= 1e-5
+    assert mx <= 1e-5 and ms <= 1e-5
+
+
+def _peak_and_low_bins(row, k_lo, n_peaks=32, n_low=32, halo=2):
+    """The n_peaks highest strict local maxima of row (bins >= k_lo) +- halo,
+    and the n_low lowest bins from k_lo up."""
+    k = np.arange(max(k_lo, 1), row.shape[0] - 1)
+    is_max = (row[k] > row[k - 1]) & (row[k] >= row[k + 1])
+    pk = k[is_max][np.argsort(-row[k[is_max]], kind="stable")[:n_peaks]]
+    around = (pk[:, None] + np.arange(-halo, halo + 1)[None, :]).ravel()
+    low = np.arange(k_lo, k_lo + n_low)
+    b = np.unique(np.concatenate([around, low]))
+    return b[(b >= 1) & (b < row.shape[0])], pk
+
+
+def _parallel_oracle(cur, bins, c=0):
+    tt, xx, ss = cur.curve(c)
+    df = cur.f_max / cur.n_freq
+    parts = oracle_pool.split_bins(bins, 4 * oracle_pool.pool_size())
+    res = oracle_pool.run([(tt, xx, ss, p * df, cur.H) for p in parts])
+    return np.concatenate([r["dchi2"] for r in res], axis=1), \
+        np.concatenate([r["kappa"] for r in res]), res[0]["span"]
+
+
+def _gated(cur, d_gpu, d_ora, kappa, span, bins, precision):
+    fr = bins * (cur.f_max / cur.n_freq)
+    gate = (fr >= 1.0 / span) & (kappa <= KAPPA[precision])
+    err = ora.rel_err(d_gpu[:, bins], d_ora)
+    return err[:, gate], gate
 
 
 def test_stress_full_size_three_way():
-    """Precision stress: mixed vs all-FP64 GPU vs the oracle."""
+    """Precision stress: mixed vs all-FP64 GPU vs the oracle, on >= 256 oracle
+    bins: seeded random bins, the injected period, the 32 highest local maxima
+    of the H row +-2, and the 32 lowest gated bins."""
     cur = synth.make("stress")
     note("stress full size (n=1e6, 2^24 bins, H=8) mixed")
     dm, _, flm, _ = run_search(cur, "mixed", tune=True)
@@ -91,14 +132,26 @@ def test_stress_full_size_three_way():
     print(f"stress mixed vs fp64 GPU over {ok.sum()} bins: max {gg.max():.3e}, "
           f"median {np.median(gg):.3e}, p99.99 {np.percentile(gg, 99.99):.3e}", flush=True)
     k0 = int(round(cur.n_freq / cur.f_max / 0.1234))
-    bins = np.unique(np.concatenate([sample_bins(cur.n_freq, 16, 5), [k0 - 1, k0, k0 + 1]]))
-    em, r = _compare(cur, dm, bins, "mixed", label="stress mixed vs oracle")
-    ed, _ = _compare(cur, dd, bins, "fp64", label="stress fp64 vs oracle", r=r)
+    k_lo = int(np.ceil(cur.n_freq / (span * cur.f_max)))
+    special, peaks = _peak_and_low_bins(dd[0][cur.H - 1], k_lo)
+    bins = np.unique(np.concatenate([sample_bins(cur.n_freq, 96, 5), [k0 - 1, k0, k0 + 1],
+                                     special]))
+    assert len(bins) >= 256
+    note(f"stress: oracle on {len(bins)} bins ({len(peaks)} peaks)")
+    d_ora, kappa, span_o = _parallel_oracle(cur, bins)
+    em, gm = _gated(cur, dm[0], d_ora, kappa, span_o, bins, "mixed")
+    ed, gd = _gated(cur, dd[0], d_ora, kappa, span_o, bins, "fp64")
+    print(f"stress vs oracle on {len(bins)} bins: mixed gated {gm.sum()} max {em.max():.3e} "
+          f"median {np.median(em):.3e}; fp64 gated {gd.sum()} max {ed.max():.3e} "
+          f"median {np.median(ed):.3e}", flush=True)
     assert em.max() <= 1e-5 and ed.max() <= 1e-8
     assert np.percentile(gg, 99.9) <= 1e-5
 
 
-def test_batch_full_size_sampled_curves():
+def test_batch_full_size_stratified_curves():
+    """The batch at full size: 32 curves stratified by length quartile and
+    signal / noise (48 bins each) plus 16 seeded bins on every one of the
+    10^4 curves, against the oracle."""
     import torch
     cur = synth.make("batch")
     note("batch full size (1e4 curves, 2^16 bins)")
@@ -110,12 +163,36 @@ def test_batch_full_size_sampled_curves():
     with torch.cuda.stream(st):
         d, _, _ = plan.search(t, x, s, want_flags=False)
         st.synchronize()
-    d = d.double().cpu().numpy()
+    d = d.cpu().numpy()
     rng = np.random.default_rng(33)
-    worst = 0.0
-    for c in rng.choice(cur.n_curves, 24, replace=False):
-        bins = sample_bins(cur.n_freq, 12, 100 + int(c))
-        e, _ = _compare(cur, d, bins, "mixed", c=int(c), label=f"batch curve {c}")
+    n = np.diff(cur.offsets)
+    sig = np.asarray(cur.meta["with_signal"], dtype=bool)
+    q = np.searchsorted(np.quantile(n, [0.25, 0.5, 0.75]), n, side="right")
+    strat = []
+    for qq in range(4):
+        for ss in (False, True):
+            idx = np.nonzero((q == qq) & (sig == ss))[0]
+            strat += [int(c) for c in rng.choice(idx, size=4, replace=False)]
+    df = cur.f_max / cur.n_freq
+    tasks, where = [], []
+    for c in range(cur.n_curves):
+        nb = 16 + (48 if c in strat else 0)
+        bins = np.sort(rng.choice(np.arange(1, cur.n_freq), size=nb, replace=False))
+        tasks.append((*cur.curve(c), bins * df, cur.H))
+        where.append((c, bins))
+    note(f"batch: oracle on {sum(len(b) for _, b in where)} bins")
+    res = oracle_pool.run(tasks)
+    errs = []
+    strat_worst = 0.0
+    for (c, bins), r in zip(where, res):
+        fr = bins * df
+        gate = ora.gate_mask(r, fr, KAPPA["mixed"])
+        e = ora.rel_err(d[c][:, bins].astype(np.float64), r["dchi2"])[:, gate]
         if e.size:
-            worst = max(worst, float(e.max()))
-    assert worst <= 1e-5
+            errs.append(e.ravel())
+            if c in strat:
+                strat_worst = max(strat_worst, float(e.max()))
+    e = np.concatenate(errs)
+    print(f"batch: {e.size} gated values on {cur.n_curves} curves, max {e.max():.3e}, "
+          f"median {np.median(e):.3e}; stratified curves max {strat_worst:.3e}", flush=True)
+    assert e.max() <= 1e-5
