@@ -78,7 +78,9 @@ def stage_roofline(cur, stages, steps_profiled, b, o, schedule):
     effective bandwidths, and the solve's FP64 rate.  Each FFT pass is a full
     read and write of the grids (a schedule with more than two passes moves
     more than the two-pass model counts); with the spreading fused into the
-    first pass, that pass is also charged the spreading's grid write."""
+    first pass, that pass is also charged the spreading's grid write; the
+    persistent search (one launch for the whole chain) is charged the whole
+    step's bytes."""
     H, nf, nc = cur.H, cur.n_freq, cur.n_curves
     n_tot = int(cur.t.shape[0])
     m = sec8d_bytes(n_tot / nc, H, nf, b, o)
@@ -90,6 +92,8 @@ def stage_roofline(cur, stages, steps_profiled, b, o, schedule):
     if schedule.get("fused_spread"):
         per_stage_bytes["fft_first"] += nc * m["spread"]
         per_stage_bytes["spread"] = 24 * n_tot
+    if schedule.get("persistent"):
+        per_stage_bytes = {"persistent": nc * m["step"]}
     ms = {k: v[0] / steps_profiled for k, v in stages.items() if v[1]}
     launches = {k: v[1] / steps_profiled for k, v in stages.items() if v[1]}
     cand = {k: ms[k] for k in per_stage_bytes if k in ms}
@@ -98,6 +102,8 @@ def stage_roofline(cur, stages, steps_profiled, b, o, schedule):
     bytes_launch = per_stage_bytes[dom] / launches[dom]
     achieved = bytes_launch / (avg_launch_ms * 1e-3) / 1e9
     fft_ms = sum(ms.get(k, 0.0) for k in ("spread", "fft_first", "fft_mid", "fft_last"))
+    if "persistent" in ms:  # one launch: no separate gridding + FFT time
+        fft_ms = step_ms = sum(ms.values())
     step_ms = sum(ms.values())
     grid_gb = nc * m["gridding_fft"] / 1e9
     step_gb = nc * m["step"] / 1e9
@@ -114,6 +120,8 @@ def stage_roofline(cur, stages, steps_profiled, b, o, schedule):
                        "gbs": round(step_gb / (step_ms * 1e-3), 1),
                        "frac": round(step_gb / (step_ms * 1e-3) / HBM_PEAK_GBS, 4)},
     }
+    if "persistent" in ms:
+        sections["gridding_fft"] = None
     if "solve" in ms:
         fl = solve_flops(H) * nf * nc
         tf = fl / (ms["solve"] * 1e-3) / 1e12
@@ -137,8 +145,11 @@ def measured_traffic(name):
     if not m:
         return {}
     meta = json.loads(m.group(1))
-    src = {"fft_first": ["fft.hip"], "fft_mid": ["fft.hip"], "fft_last": ["fft.hip"],
-           "solve": ["solve.hip", "solve_bin.h"], "spread": ["spread.hip", "es_kernel.h"]}
+    fft = ["fft.hip", "fft_tile.h"]
+    src = {"fft_first": fft, "fft_mid": fft, "fft_last": fft,
+           "solve": ["solve.hip", "solve_bin.h"],
+           "spread": ["spread.hip", "spread_tile.h", "es_kernel.h"],
+           "persistent": ["persist.hip", "fft_tile.h", "spread_tile.h", "solve_bin.h"]}
     out = {}
     for st, nbytes in meta.get("bytes_per_launch", {}).items():
         h = hashlib.sha256()

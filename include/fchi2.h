@@ -80,6 +80,20 @@ typedef enum {
                                       results are the same bit for bit; the
                                       autotuner may change it; not for band
                                       plans                                  */
+#define FCHI2_PERSISTENT 16u       /* search all curves in one persistent
+                                      launch: workgroups claim curves from a
+                                      device work queue and run each curve's
+                                      whole chain in a workspace slot; the
+                                      results are the same bit for bit; used
+                                      where the schedule allows it (MIXED,
+                                      H <= 8, no band, no backward, L =
+                                      4 n_freq <= 2^20, FFT passes of
+                                      2^12-element tiles with 2^5..2^9 rows,
+                                      spreading tiles of 2^10 or 2^11 cells),
+                                      else ignored; the autotuner may change
+                                      it, and times it itself only for
+                                      batches with at least as many curves
+                                      as workgroups resident on the device  */
 
 /* Largest H supported by the search (fchi2_search, _curves, _coeffs,
  * _noalloc, fchi2_autotune, fchi2_top_peaks).  Up to 8 the per-bin solve
@@ -113,7 +127,8 @@ typedef struct {
                                 max t_span) (see below)                       */
   int32_t precision;         /* fchi2_precision_t                             */
   uint32_t flags;            /* FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH |
-                                FCHI2_FUSED_SPREAD | FCHI2_WIDE_SOLVE         */
+                                FCHI2_FUSED_SPREAD | FCHI2_WIDE_SOLVE |
+                                FCHI2_PERSISTENT                              */
   int32_t kernel_width;      /* spreading kernel taps, 0 = default
                                 (14 for FP64, 10 for MIXED); 4..16; or 1 =
                                 floor gridding as printed in Section 3b (each
@@ -483,7 +498,8 @@ fchi2_status_t fchi2_detrend(fchi2_plan_t plan, const double* t, const double* x
 #define FCHI2_PROF_BWD_FINAL 9
 #define FCHI2_PROF_TOP_MERGE 10
 #define FCHI2_PROF_FINE 11
-#define FCHI2_PROF_STAGES 12
+#define FCHI2_PROF_PERSISTENT 12
+#define FCHI2_PROF_STAGES 13
 fchi2_status_t fchi2_profile(fchi2_plan_t plan, int32_t enable);
 fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* launches);
 
@@ -514,7 +530,8 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
  * digits 1..4 (0 if unused), info[5] = log2 spreading tile, info[6] = curves
  * per wave, info[7] = kernel width, and with n >= 12 info[8..11] = log2 FFT
  * tile elements of passes 1..4 (0 if unused), with n >= 13 info[12] = 1 if
- * the spreading runs inside the first FFT pass.  n must be >= 8.
+ * the spreading runs inside the first FFT pass, with n >= 14 info[13] = 1 if
+ * searches run as one persistent launch.  n must be >= 8.
  */
 fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n);
 

@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfchi2.so")
-SOURCES = ["spread.hip", "fft.hip", "solve.hip", "signif.hip", "fine.hip", "detrend.hip",
-           "backward.hip", "peaks.hip", "host.hip"]
+SOURCES = ["persist.hip", "solve.hip", "fft.hip", "signif.hip", "spread.hip", "fine.hip",
+           "detrend.hip", "backward.hip", "peaks.hip", "host.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

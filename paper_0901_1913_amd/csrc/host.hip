@@ -298,6 +298,14 @@ struct fchi2_plan_s {
   int log_tile = 10;
   // Spreading fused into the first FFT pass (no spread grid in memory).
   int fused = 0;
+  // Persistent batched search: one launch, curves claimed from a device work
+  // queue by n_slots workgroups, each with a slot of the workspace (its
+  // grids, spectra and tile table) at off_gA + slot * slot_bytes.
+  int persist = 0;
+  int n_slots = 0;
+  int n_slots_device = 0;  // workgroups resident on the whole device
+  size_t slot_bytes = 0, slot_gB = 0, slot_zc = 0, slot_tb = 0;
+  size_t off_queue = 0;
   double eps_piv = 0.0;
   int wave = 1;
   int wave_max = 1;        // the workspace is sized for this many curves
@@ -428,6 +436,76 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
 // Whether the forward chain spreads inside the first FFT pass.
 bool use_fused(const fchi2_plan_s* pl) { return pl->fused && pl->fp.np >= 2 && !pl->g.band; }
 
+// Whether the persistent kernel can run split f with spreading tiles of
+// 2^tile cells: mixed precision, H <= 8, no band, no kept spectra, grids of
+// at most 2^20 cells (one workgroup transforms a whole curve), every pass a
+// tile of 2^12 elements of 2^5..2^9 rows, spreading tiles of 2^10 or 2^11.
+bool persist_ok(const fchi2_plan_s* pl, const FftPlan& f, int tile) {
+  if (pl->n_slots < 1 || pl->fp64 || pl->g.band || pl->g.H > kHMax) return false;
+  if (pl->g.L > ((int64_t)1 << 20)) return false;
+  if (pl->desc.flags & (FCHI2_KEEP_FOR_BACKWARD | FCHI2_WIDE_SOLVE)) return false;
+  if (f.np < 2 || (tile != 10 && tile != 11)) return false;
+  for (int q = 1; q <= f.np; ++q)
+    if (f.le[q] != 12 || f.logn[q] < 5 || f.logn[q] > 9) return false;
+  return true;
+}
+bool use_persist(const fchi2_plan_s* pl) {
+  return pl->persist && persist_ok(pl, pl->fp, pl->log_tile);
+}
+// Whether the autotuner times the persistent schedule: only for batches that
+// fill every resident workgroup at the start.  One workgroup runs a whole
+// curve, so a few curves would leave most of the device idle;
+// FCHI2_PERSISTENT still forces it.
+bool persist_worth_timing(const fchi2_plan_s* pl) {
+  return pl->n_slots_device > 0 && pl->desc.n_curves >= pl->n_slots_device;
+}
+
+// The persistent search of curves [cbeg, cend) (moments already computed).
+fchi2_status_t enqueue_persistent(fchi2_plan_s* pl, int cbeg, int cend, const double* t,
+                                  const double* x, const double* sigma, char* ws, void* dchi2,
+                                  uint8_t* flags, hipStream_t st) {
+  PersistArgs a{};
+  a.t = t;
+  a.x = x;
+  a.sigma = sigma;
+  a.mom = (const Moments*)(ws + pl->off_mom);
+  a.g = pl->g;
+  const FftPlan& fp = pl->fp;
+  for (int q = 1; q <= fp.np; ++q) {
+    FftPassArgs& f = a.fa[q];
+    f.kind = (q == fp.np) ? PASS_FIRST : (q == 1 ? PASS_LAST : PASS_MID);
+    f.mode = MODE_FWD;
+    f.np = fp.np;
+    f.q = q;
+    for (int d = 0; d <= kMaxPasses; ++d) f.logn[d] = fp.logn[d];
+    f.logL = fp.logL;
+    f.curve0 = 0;
+  }
+  a.fa[0] = a.fa[1];
+  a.tws = (const cplx<double>*)pl->d_tw_stage;
+  a.twsm = (const cplx<double>*)pl->d_tw_small;
+  a.D = (const cplx<double>*)pl->d_D;
+  a.curve_base = cbeg;
+  a.n_curves = cend - cbeg;
+  a.log_tile = pl->log_tile;
+  a.ntb = (int)((pl->g.L >> pl->log_tile) * pl->g.laps) + 2;
+  a.slots = ws + pl->off_gA;
+  a.slot_bytes = pl->slot_bytes;
+  a.off_gB = pl->slot_gB;
+  a.off_zc = pl->slot_zc;
+  a.off_tb = pl->slot_tb;
+  a.next = (int*)(ws + pl->off_queue);
+  a.eps = pl->eps_piv;
+  a.out = (float*)dchi2;
+  a.flags = flags;
+  const int n = cend - cbeg;
+  PROF_BEGIN(FCHI2_PROF_PERSISTENT);
+  hipError_t e = launch_persistent(a, n < pl->n_slots ? n : pl->n_slots, st);
+  if (e != hipSuccess) return hip_fail(e, "persistent search");
+  PROF_END();
+  return FCHI2_OK;
+}
+
 // The whole forward chain for curves [cbeg, cend), in waves of pl->wave.
 fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double* t,
                               const double* x, const double* sigma, char* ws, void* dchi2,
@@ -440,6 +518,8 @@ fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double
                                 mom + cbeg, chi2_0 ? chi2_0 + cbeg : nullptr, st);
   if (e != hipSuccess) return hip_fail(e, "moments");
   PROF_END();
+  if (use_persist(pl) && !coef)
+    return enqueue_persistent(pl, cbeg, cend, t, x, sigma, ws, dchi2, flags, st);
   const bool keep = pl->desc.flags & FCHI2_KEEP_FOR_BACKWARD;
   const size_t zc_curve = (size_t)pl->g.P * 2 * pl->g.n_freq * pl->elem;
   for (int c0 = cbeg; c0 < cend; c0 += pl->wave) {
@@ -634,12 +714,12 @@ fchi2_status_t check_ws(fchi2_plan_s* pl, void* ws, size_t bytes) {
 // candidate tried.
 template <typename Run>
 fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
-                         const std::vector<int>& waves, bool allow_fused, Run run,
-                         hipStream_t st, float& best_ms, FftPlan& best_f, int& best_tile,
-                         int& best_wave, int& best_fused) {
+                         const std::vector<int>& waves, bool allow_fused, bool allow_persist,
+                         Run run, hipStream_t st, float& best_ms, FftPlan& best_f,
+                         int& best_tile, int& best_wave, int& best_fused, int& best_persist) {
   struct Cand {
     FftPlan f;
-    int tile, wave, fused;
+    int tile, wave, fused, persist;
     float ms;
   };
   hipEvent_t e0, e1;
@@ -656,6 +736,7 @@ fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
     pl->log_tile = c.tile;
     pl->wave = c.wave;
     pl->fused = c.fused;
+    pl->persist = c.persist;
     apply_fft_plan(pl, c.f);
     hipError_t e = hipEventRecord(e0, st);
     if (e == hipSuccess) res = run();
@@ -666,12 +747,17 @@ fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
     if (e != hipSuccess) res = hip_fail(e, "autotune timing");
   };
   std::vector<Cand> cands;
-  for (const FftPlan& f : splits)
+  for (const FftPlan& f : splits) {
     for (int wave : waves) {
-      for (int tile : {10, 11, 12, 13}) cands.push_back(Cand{f, tile, wave, 0, 1e30f});
+      for (int tile : {10, 11, 12, 13}) cands.push_back(Cand{f, tile, wave, 0, 0, 1e30f});
       // The fused schedule has no spreading tile.
-      if (allow_fused && f.np >= 2) cands.push_back(Cand{f, 10, wave, 1, 1e30f});
+      if (allow_fused && f.np >= 2) cands.push_back(Cand{f, 10, wave, 1, 0, 1e30f});
     }
+    // The persistent search has no waves.
+    for (int tile : {10, 11})
+      if (allow_persist && persist_ok(pl, f, tile) && persist_worth_timing(pl))
+        cands.push_back(Cand{f, tile, waves[0], 0, 1, 1e30f});
+  }
   for (Cand& c : cands) {
     for (int rep = 0; rep < 3 && res == FCHI2_OK; ++rep) {
       float ms = 0.f;
@@ -701,6 +787,7 @@ fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
         best_tile = cands[bi].tile;
         best_wave = cands[bi].wave;
         best_fused = cands[bi].fused;
+        best_persist = cands[bi].persist;
       }
     }
   }
@@ -769,7 +856,7 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   if (d.precision != FCHI2_FP64 && d.precision != FCHI2_MIXED)
     return fail(FCHI2_ERR_ARG, "precision must be FCHI2_FP64 or FCHI2_MIXED");
   if (d.flags & ~(uint32_t)(FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH | FCHI2_FUSED_SPREAD |
-                            FCHI2_WIDE_SOLVE))
+                            FCHI2_WIDE_SOLVE | FCHI2_PERSISTENT))
     return fail(FCHI2_ERR_ARG, "unknown flag bits 0x%x", d.flags);
   if ((d.H > kHMax || (d.flags & FCHI2_WIDE_SOLVE)) && (d.flags & FCHI2_KEEP_FOR_BACKWARD))
     return fail(FCHI2_ERR_UNSUPPORTED, "backward needs H <= %d (the register solver)", kHMax);
@@ -863,6 +950,7 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   }
   pl->log_tile = 10;
   pl->fused = (d.flags & FCHI2_FUSED_SPREAD) ? 1 : 0;
+  pl->persist = (d.flags & FCHI2_PERSISTENT) ? 1 : 0;
   apply_fft_plan(pl, pl->fp);
 
   // Waves: bound the two grid buffers to ~8 GiB unless the caller chose.
@@ -908,7 +996,35 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
     pl->off_dw = off;
     off = align256(off + sizeof(double) * (size_t)d.n_curves * pl->blocks_per_curve);
   }
+  // The persistent search's work-queue counter.
+  pl->off_queue = off;
+  off = align256(off + sizeof(int));
   pl->ws_bytes = off;
+
+  // Persistent search slots: as many workgroups as fit on the device at once
+  // (no more than there are curves), each with one pair's grids, all pairs'
+  // spectra and the tile table (tiles of 2^10 cells), laid out over the wave
+  // buffers (gA, gB, zc), which the persistent search does not otherwise use;
+  // never more slots than fit there.
+  if (!pl->fp64 && !g.band && d.H <= kHMax && !keep) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        persist_occupancy(d.H, &per_cu) == hipSuccess && cus > 0 && per_cu > 0) {
+      const size_t grid1 = (size_t)g.L * pl->elem;
+      pl->slot_gB = align256(grid1);
+      pl->slot_zc = pl->slot_gB + align256(grid1);
+      pl->slot_tb = pl->slot_zc + align256(zc_curve);
+      pl->slot_bytes = align256(pl->slot_tb + tile_bounds_bytes(g, 10, 1));
+      const size_t room = pl->off_queue - pl->off_gA;
+      int64_t n = (int64_t)cus * per_cu;
+      pl->n_slots_device = (int)n;
+      n = std::min<int64_t>(n, d.n_curves);
+      n = std::min<int64_t>(n, (int64_t)(room / pl->slot_bytes));
+      pl->n_slots = (int)n;
+    }
+    (void)hipGetLastError();
+  }
 
   // Device tables.
   hipStream_t st = (hipStream_t)stream;
@@ -1342,17 +1458,19 @@ fchi2_status_t fchi2_autotune_multi(fchi2_plan_t plan, const double* t, const do
   float best_ms = 1e30f;
   FftPlan best_f = pl->fp;
   int best_tile = pl->log_tile, best_wave = pl->wave, best_fused = pl->fused;
+  int best_persist = pl->persist;
   fchi2_status_t res = tune_loop(
-      pl, splits, waves, false,
+      pl, splits, waves, false, false,
       [&]() {
         return enqueue_multi(pl, multi_layout(pl, n_sources), t, sigma, x, scale, n_sources,
                              (char*)workspace, dchi2, nullptr, nullptr, st);
       },
-      st, best_ms, best_f, best_tile, best_wave, best_fused);
+      st, best_ms, best_f, best_tile, best_wave, best_fused, best_persist);
   pl->prof = prof;
   pl->log_tile = best_tile;
   pl->wave = best_wave;
   pl->fused = best_fused;
+  pl->persist = best_persist;
   apply_fft_plan(pl, best_f);
   pl->last_ws = nullptr;
   ++pl->gen;
@@ -1450,14 +1568,20 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
         const char* tag = strstr(line, " | ");
         if (!tag || strncmp(line, key, strlen(key)) != 0 || line + strlen(key) != tag) continue;
         int np = 0, ln[kMaxPasses + 1] = {0}, le[kMaxPasses + 1] = {0}, tile = 0, wave = 0;
-        int fz = 0;  // lines without the field name the unfused schedule
-        if (sscanf(tag, " | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d fused=%d", &np,
-                   &ln[1], &ln[2], &ln[3], &ln[4], &le[1], &le[2], &le[3], &le[4], &tile, &wave,
-                   &fz) >= 11 &&
+        // Lines without the fused / persist fields name the staged schedule.
+        int fz = 0, ps = 0;
+        if (sscanf(tag,
+                   " | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d fused=%d persist=%d",
+                   &np, &ln[1], &ln[2], &ln[3], &ln[4], &le[1], &le[2], &le[3], &le[4], &tile,
+                   &wave, &fz, &ps) >= 11 &&
             tile >= 10 && tile <= 13 && wave >= 1 && wave <= pl->wave_max &&
-            (fz == 0 || (fz == 1 && !pl->g.band))) {
+            (fz == 0 || (fz == 1 && !pl->g.band)) && (ps == 0 || ps == 1)) {
           found = apply(ln, le, np, tile, wave);
-          if (found) pl->fused = fz;
+          if (found && ps == 1 && !persist_ok(pl, pl->fp, tile)) found = false;
+          if (found) {
+            pl->fused = fz;
+            pl->persist = ps;
+          }
         }
       }
       fclose(fh);
@@ -1473,28 +1597,32 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
   float best_ms = 1e30f;
   FftPlan best_f = pl->fp;
   int best_tile = pl->log_tile, best_wave = pl->wave, best_fused = pl->fused;
+  int best_persist = pl->persist;
   const bool allow_fused = !pl->g.band;
   fchi2_status_t res = tune_loop(
-      pl, splits, waves, allow_fused,
+      pl, splits, waves, allow_fused, true,
       [&]() {
         return enqueue_search(pl, 0, pl->desc.n_curves, t, x, sigma, (char*)workspace, dchi2,
                               nullptr, nullptr, st);
       },
-      st, best_ms, best_f, best_tile, best_wave, best_fused);
+      st, best_ms, best_f, best_tile, best_wave, best_fused, best_persist);
   pl->prof = prof;
   pl->log_tile = best_tile;
   pl->wave = best_wave;
   pl->fused = best_fused;
+  pl->persist = best_persist;
   apply_fft_plan(pl, best_f);
   pl->last_ws = nullptr;
   ++pl->gen;
   if (res != FCHI2_OK) return res;
   if (cache_path) {
     if (FILE* fh = fopen(cache_path, "a")) {
-      fprintf(fh, "%s | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d fused=%d ms=%.4f\n",
+      fprintf(fh,
+              "%s | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d fused=%d persist=%d "
+              "ms=%.4f\n",
               key, best_f.np, best_f.logn[1], best_f.logn[2], best_f.logn[3], best_f.logn[4],
               best_f.le[1], best_f.le[2], best_f.le[3], best_f.le[4], best_tile, best_wave,
-              best_fused, best_ms);
+              best_fused, best_persist, best_ms);
       fclose(fh);
     }
   }
@@ -1511,6 +1639,7 @@ fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n) {
   info[7] = plan->g.w;
   for (int q = 1; q <= kMaxPasses && 7 + q < n; ++q) info[7 + q] = q <= plan->fp.np ? plan->fp.le[q] : 0;
   if (n > 12) info[12] = use_fused(plan) ? 1 : 0;
+  if (n > 13) info[13] = use_persist(plan) ? 1 : 0;
   return FCHI2_OK;
 }
 

@@ -54,6 +54,40 @@ hipError_t launch_fft_pass(bool fp64, const FftPassArgs& a, int logn, int logt, 
                            void* out, const Moments* mom, const Geom& g, const void* tws,
                            const void* twsm, int n_curves, int64_t ncols, hipStream_t st);
 
+// Persistent batched search (MIXED plans, H <= 8, FFT splits of 4096-element
+// tiles with 2^5..2^9 rows per pass, spreading tiles of 2^10 or 2^11 cells):
+// one launch of n_slots workgroups takes curves [curve_base, curve_base +
+// n_curves) from the queue counter *next and runs each one's whole chain in
+// its own slot of slot_bytes (gA at 0, gB at off_gB, spectra at off_zc, tile
+// table at off_tb).  The moments must be computed first.
+struct PersistArgs {
+  const double* t;
+  const double* x;
+  const double* sigma;
+  const Moments* mom;
+  Geom g;
+  // fa[q]: the arguments of forward pass q = 1..np (kind, split, logL), with
+  // curve0 = 0: the pass reads its curve's moments at mom[c].  Prebuilt per
+  // pass so that the kernel indexes the split from its argument block.
+  FftPassArgs fa[kMaxPasses + 1];
+  const cplx<double>* tws;
+  const cplx<double>* twsm;
+  const cplx<double>* D;
+  int curve_base;
+  int n_curves;
+  int log_tile;
+  int ntb;
+  char* slots;
+  size_t slot_bytes, off_gB, off_zc, off_tb;
+  int* next;
+  double eps;
+  float* out;
+  uint8_t* flags;
+};
+size_t persist_smem_bytes();
+hipError_t persist_occupancy(int H, int* blocks_per_cu);
+hipError_t launch_persistent(const PersistArgs& a, int n_slots, hipStream_t st);
+
 // Deconvolution / origin-shift factors D[k] = exp(-2 pi i k c_off / L) / phi_hat(k).
 // FP64 complex [n_freq].
 hipError_t launch_deconv_init(void* D, const Geom& g, const double* gl_x, const double* gl_w,

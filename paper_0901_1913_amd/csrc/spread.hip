@@ -29,12 +29,11 @@
 #include "fchi2_internal.h"
 #include "launch.h"
 #include "es_kernel.h"
+#include "spread_tile.h"
 
 namespace fchi2 {
 
 namespace {
-
-constexpr int kNT = 256;
 
 // Sum over the block in a fixed order (wave butterflies, then the four wave
 // sums in order): deterministic, two barriers.  red holds kNT / 64 values.
@@ -184,32 +183,6 @@ __global__ __launch_bounds__(64) void k_moments_fin(const double* __restrict__ t
   if (chi2_out) chi2_out[c] = (fl & kCurveFatal) ? NAN : M2 / sc2;
 }
 
-__device__ __forceinline__ double cell_pos(const double* __restrict__ t, int64_t i, double T0,
-                                           double df, int m, double L, double c_off,
-                                           bool flr) {
-  return cell_at(t[i], T0, df, m, L, c_off, flr);
-}
-
-// Tile -> point-range table.  For harmonic m and tile t of B cells, the
-// points a tile may need are those with position in
-// [x_t, x_{t+2}), x_t = t B - w/2 - 2 (a superset of the kernel footprint).
-// tb[t] = first point index i (relative to the curve) with pos_i >= x_t.  The
-// intervals (pos_{i-1}, pos_i] partition the line, so thread i writes exactly
-// the entries whose x_t falls in its interval: one scatter, no searches.
-// Entries stop at tile_limit(): tiles past it hold no point of harmonic m.
-// Last table entry written for harmonic m: the tile after the one holding the
-// last point's footprint, plus the two-tile lookahead of the spreading.
-__device__ __forceinline__ int64_t tile_limit_of(double t_last, const Moments& mo,
-                                                 const Geom& g, int m, int log_tile) {
-  const double last = cell_at(t_last, mo.T0, g.df, m, (double)g.L, (double)g.c_off, g.w == 1);
-  return (int64_t)floor((last + (double)(g.w / 2 + 2)) / (double)((int64_t)1 << log_tile)) + 3;
-}
-
-__device__ __forceinline__ int64_t tile_limit(const double* __restrict__ t, const Moments& mo,
-                                              const Geom& g, int m, int log_tile) {
-  return tile_limit_of(t[mo.start + mo.n - 1], mo, g, m, log_tile);
-}
-
 __global__ __launch_bounds__(kNT) void k_tile_bounds(const double* __restrict__ t,
                                                      const Moments* __restrict__ mom, Geom g,
                                                      int curve0, int log_tile, int ntb,
@@ -219,29 +192,12 @@ __global__ __launch_bounds__(kNT) void k_tile_bounds(const double* __restrict__ 
   const Moments mo = mom[curve0 + cw];
   if (mo.flags & kCurveFatal) return;
   const int64_t il = (int64_t)blockIdx.x * kNT + threadIdx.x;
-  if (il > mo.n) return;
-  const double Ld = (double)g.L, coff = (double)g.c_off;
-  const double B = (double)((int64_t)1 << log_tile);
-  const double shift = (double)(g.w / 2 + 2);
-  int64_t t_min, t_max;
-  if (il == 0) {
-    t_min = 0;
-  } else {
-    const double lo = cell_pos(t, mo.start + il - 1, mo.T0, g.df, m, Ld, coff, g.w == 1);
-    t_min = (int64_t)floor((lo + shift) / B) + 1;
-  }
-  if (il == mo.n) {
-    t_max = tile_limit(t, mo, g, m, log_tile);
-  } else {
-    const double hi = cell_pos(t, mo.start + il, mo.T0, g.df, m, Ld, coff, g.w == 1);
-    t_max = (int64_t)floor((hi + shift) / B);
-  }
-  if (t_min < 0) t_min = 0;
-  if (t_max > ntb - 1) t_max = ntb - 1;
-  int32_t* row = tb + ((int64_t)cw * (2 * g.H) + (m - 1)) * ntb;
-  for (int64_t q = t_min; q <= t_max; ++q) row[q] = (int32_t)il;
+  tile_bounds_point(t, mo, g, cw, m, il, log_tile, ntb, tb);
 }
 
+// Blocks of one curve (wave slot blockIdx.z) stride over the tiles below each
+// pair's nonzero extent, pair after pair (cells beyond the extent are never
+// read).
 template <typename S, int LOGB, bool BAND>
 __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
                                                 const double* __restrict__ x,
@@ -250,155 +206,23 @@ __global__ __launch_bounds__(kNT) void k_spread(const double* __restrict__ t,
                                                 int curve0, const int32_t* __restrict__ tb,
                                                 int ntb, int share_tb,
                                                 cplx<S>* __restrict__ grid) {
-  constexpr bool EXACT = sizeof(S) == 8;
-  constexpr int B = 1 << LOGB;
-  constexpr int CPT = B / kNT;
-  constexpr int CH = 1024;
-  __shared__ double s_p[CH];  // cell coordinate relative to the tile start (exact)
-  __shared__ double2 s_v[CH];  // strengths of the real and imaginary parts
-  __shared__ int s_first[kNT];
-
-  const int tid = threadIdx.x;
+  __shared__ SpreadSmem<LOGB> sh;
   const int cw = blockIdx.z;
   const Moments mo = mom[curve0 + cw];
   if (mo.flags & kCurveFatal) return;
-  // Work items: the tiles below each pair's nonzero extent, pair after pair
-  // (cells beyond the extent are never read); blocks stride over them.
   int64_t items = 0;
   for (int q = 0; q < g.P; ++q) items += pair_extent(mo, g, q) >> LOGB;
-  const double t_last = t[mo.start + mo.n - 1];
   for (int64_t wi = blockIdx.x; wi < items; wi += gridDim.x) {
-  int p = 0;
-  int64_t tile = wi;
-  for (;;) {
-    const int64_t nt = pair_extent(mo, g, p) >> LOGB;
-    if (tile < nt) break;
-    tile -= nt;
-    ++p;
-  }
-  const int64_t a0 = tile * B;
-
-  const int hw = g.w / 2;
-  const double two_over_w = 2.0 / (double)g.w;
-  const double hreach = (double)(hw + 1);
-  const double beta = g.beta;
-  const double Ld = (double)g.L;
-  const double coff = (double)g.c_off;
-  const int64_t pa = mo.start;
-
-  double acc_re[CPT], acc_im[CPT];
-#pragma unroll
-  for (int u = 0; u < CPT; ++u) {
-    acc_re[u] = 0.0;
-    acc_im[u] = 0.0;
-  }
-
-  // The grid is periodic in L cells: positions are kept unwrapped (the
-  // phase m u of a long curve may span several periods) and the tile table
-  // runs over g.laps periods, so the tile gathers its points lap after lap
-  // (in index order: positions grow with t).
-  const int64_t ntile = g.L >> LOGB;
-  for (int comp = 0; comp < 2; ++comp) {
-    const int m = g.comp_m[p][comp];
-    if (m == 0) continue;
-    if (comp == 1 && m == g.comp_m[p][0]) continue;  // shared with component 0
-    const bool both = (comp == 0) && (g.comp_m[p][1] == m);
-    const int kind_a = g.comp_kind[p][comp];
-    const int kind_b = both ? g.comp_kind[p][1] : -1;
-    const int32_t* row = tb + ((int64_t)(share_tb ? 0 : cw) * (2 * g.H) + (m - 1)) * ntb;
-    // No point of harmonic m reaches tiles past tile_limit - 2.
-    const int64_t lim = tile_limit_of(t_last, mo, g, m, LOGB);
-   for (int lap = 0; lap < g.laps; ++lap) {
-    const int64_t ut = tile + (int64_t)lap * ntile;  // tile on the unwrapped axis
-    if (ut + 2 > lim) break;
-    const int64_t i_lo = pa + row[ut], i_hi = pa + row[ut + 2];
-    if (i_hi <= i_lo) continue;  // no points in this lap
-    const int64_t base = a0 + (int64_t)lap * g.L;
-
-    for (int64_t ch = i_lo; ch < i_hi; ch += CH) {
-      const int cnt = (int)((i_hi - ch) < CH ? (i_hi - ch) : CH);
-      for (int q = tid; q < cnt; q += kNT) {
-        const int64_t i = ch + q;
-        // floor gridding: pos is an integer and the kernel below is
-        // exp(0) = 1 at d = 0 and 0 at |d| >= 1 (w = 1)
-        const double pos = cell_pos(t, i, mo.T0, g.df, m, Ld, coff, g.w == 1);
-        const double si = sigma[i];
-        const double w = 1.0 / (si * si);
-        const double wy = w * (x[i + mo.xshift] - mo.xbar);
-        const double sa = (kind_a == 0) ? w : wy;
-        double sre, sim;
-        if constexpr (BAND) {
-          // Band plan: strength times exp(+2 pi i kc m u), kc = k0 + n_freq/2
-          // the band's middle bin, so that grid bin j (j - L for j >= L/2)
-          // is bin kc + j of the search.  The phase kc m u in cycles is
-          // reduced modulo 1 from the FP64 product and its exact rounding
-          // residual.
-          const double km = (double)((g.k0 + g.n_freq / 2) * (int64_t)m);
-          const double u = (t[i] - mo.T0) * g.df;
-          const double ph = km * u;
-          const double r = fma(km, u, -ph);
-          double fr = (ph - floor(ph)) + r;
-          fr -= floor(fr);
-          double sn, cs;
-          sincospi(2.0 * fr, &sn, &cs);
-          sre = sa * cs;
-          sim = sa * sn;
-        } else if (comp == 0) {
-          sre = sa;
-          sim = both ? ((kind_b == 0) ? w : wy) : 0.0;
-        } else {
-          sre = 0.0;
-          sim = sa;
-        }
-        // pos - base is exact (a multiple of pos's ulp, smaller than pos),
-        // and so is jl - s_p below: the same kernel argument as jl - cell - frac.
-        s_p[q] = pos - (double)base;
-        s_v[q] = make_double2(sre, sim);
-      }
-      __syncthreads();
-      // Cell jl takes the points with floor(p) in [jl - hw - 1, jl + hw], i.e.
-      // jl - hw - 1 <= p < jl + hw + 1.  The first of them is found by binary
-      // search for every (B / 256)-th cell (one search per thread); cells in
-      // between advance from it.
-      {
-        const int cs = tid * (B / kNT);
-        int lo = 0, hi = cnt;
-        const double key = (double)(cs - hw - 1);
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (s_p[mid] < key) lo = mid + 1;
-          else hi = mid;
-        }
-        s_first[tid] = lo;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < CPT; ++u) {
-        const int jl = tid + u * kNT;
-        // with d = jl - p the window is -(hw + 1) < d <= hw + 1
-        const double cl = (double)jl;
-        int q = s_first[jl / (B / kNT)];
-        while (q < cnt && cl - s_p[q] > hreach) ++q;
-        double ar = acc_re[u], ai = acc_im[u];
-        for (int r = q; r < cnt; ++r) {
-          const double d = cl - s_p[r];
-          if (d <= -hreach) break;
-          const double phi = es_kernel<EXACT>(d * two_over_w, beta);
-          const double2 v = s_v[r];
-          ar += phi * v.x;
-          ai += phi * v.y;
-        }
-        acc_re[u] = ar;
-        acc_im[u] = ai;
-      }
-      __syncthreads();
+    int p = 0;
+    int64_t tile = wi;
+    for (;;) {
+      const int64_t nt = pair_extent(mo, g, p) >> LOGB;
+      if (tile < nt) break;
+      tile -= nt;
+      ++p;
     }
-   }
-  }
-
-  cplx<S>* out = grid + ((int64_t)cw * g.P + p) * g.L + a0;
-#pragma unroll
-  for (int u = 0; u < CPT; ++u) out[tid + u * kNT] = cmk<S>((S)acc_re[u], (S)acc_im[u]);
+    spread_tile<S, LOGB, BAND>(t, x, sigma, mo, g, cw, tb, ntb, share_tb, p, tile,
+                               grid + ((int64_t)cw * g.P + p) * g.L + (tile << LOGB), sh, threadIdx.x);
   }
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfchi2.so")
 
 OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = range(6)
 FP64, MIXED = 0, 1
-KEEP_FOR_BACKWARD, GRAPH, FUSED_SPREAD, WIDE_SOLVE = 1, 2, 4, 8
+KEEP_FOR_BACKWARD, GRAPH, FUSED_SPREAD, WIDE_SOLVE, PERSISTENT = 1, 2, 4, 8, 16
 NOALLOC_SCRATCH_BYTES = 64 << 20
 H_MAX = 16
 H_MAX_REGISTER = 8
@@ -40,7 +40,7 @@ EXPORTS = (
 )
 PROF_STAGES = ("moments", "spread", "fft_first", "fft_mid", "fft_last", "solve",
                "bwd_solve", "bwd_fft", "bwd_gather", "bwd_final", "top_merge",
-               "fine")
+               "fine", "persistent")
 
 
 class PlanDesc(ctypes.Structure):
@@ -211,7 +211,8 @@ class Plan:
                  precision: str = "mixed", keep_for_backward: bool = False,
                  graph: bool = False, kernel_width: int = 0, curves_per_wave: int = 0,
                  first_bin: int = 0, oversampling: float = 0.0, t_span=None,
-                 fused_spread: bool = False, wide_solve: bool = False, stream=None):
+                 fused_spread: bool = False, wide_solve: bool = False,
+                 persistent: bool = False, stream=None):
         torch = _torch()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         if off.ndim != 1 or off.shape[0] < 2:
@@ -220,7 +221,8 @@ class Plan:
             raise ValueError("precision must be 'mixed' or 'fp64'")
         self._off = off
         flags = ((KEEP_FOR_BACKWARD if keep_for_backward else 0) | (GRAPH if graph else 0)
-                 | (FUSED_SPREAD if fused_spread else 0) | (WIDE_SOLVE if wide_solve else 0))
+                 | (FUSED_SPREAD if fused_spread else 0) | (WIDE_SOLVE if wide_solve else 0)
+                 | (PERSISTENT if persistent else 0))
         desc = PlanDesc(
             n_curves=off.shape[0] - 1,
             offsets=off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -576,13 +578,14 @@ class Plan:
 
     def info(self) -> dict:
         """The plan's schedule: FFT radices, spreading tile, wave, kernel width."""
-        arr = (ctypes.c_int32 * 13)()
-        _check(lib().fchi2_plan_info(self._h, arr, 13))
+        arr = (ctypes.c_int32 * 14)()
+        _check(lib().fchi2_plan_info(self._h, arr, 14))
         np_ = int(arr[0])
         return {"fft_log_radices": [int(arr[q]) for q in range(1, np_ + 1)],
                 "fft_log_tiles": [int(arr[7 + q]) for q in range(1, np_ + 1)],
                 "spread_tile": 1 << int(arr[5]), "curves_per_wave": int(arr[6]),
-                "kernel_width": int(arr[7]), "fused_spread": bool(arr[12])}
+                "kernel_width": int(arr[7]), "fused_spread": bool(arr[12]),
+                "persistent": bool(arr[13])}
 
     def profile(self, enable: bool = True):
         """Start (or stop) recording HIP event pairs around every launch."""

@@ -1,4 +1,5 @@
 """Helpers for the GPU tests: run the HIP path through the C ABI binding."""
+import os
 import sys
 
 import numpy as np
@@ -7,9 +8,15 @@ from paper_0901_1913_amd import fchi2 as F
 
 
 def note(msg):
-    """Name the case before a GPU step (flushed so a crash still shows it)."""
+    """Name the case before a GPU step (flushed so a crash still shows it).
+    With FCHI2_TEST_PROGRESS set to a file path, the line is also appended
+    there (pytest holds a test's own output until the test ends)."""
     print(f"[gpu] {msg}", flush=True)
     sys.stdout.flush()
+    path = os.environ.get("FCHI2_TEST_PROGRESS")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(f"[gpu] {msg}\n")
 
 
 def to_dev(curves):

@@ -23,10 +23,23 @@ def pool_size():
 
 
 def run(tasks):
-    """tasks: list of (t, x, sigma, freqs, H); returns the oracle dicts."""
+    """tasks: list of (t, x, sigma, freqs, H); returns the oracle dicts (in
+    task order), noting progress every tenth of the tasks."""
     import multiprocessing as mp
+    from tests.gpu_util import note
+    out = [None] * len(tasks)
+    step = max(1, len(tasks) // 10)
     with mp.get_context("fork").Pool(pool_size()) as pool:
-        return pool.map(_task, tasks, chunksize=1)
+        for done, (i, r) in enumerate(pool.imap_unordered(_indexed, enumerate(tasks)), 1):
+            out[i] = r
+            if done % step == 0 or done == len(tasks):
+                note(f"oracle: {done}/{len(tasks)} tasks done")
+    return out
+
+
+def _indexed(item):
+    i, args = item
+    return i, _task(args)
 
 
 def split_bins(bins, parts):
