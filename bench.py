@@ -132,11 +132,36 @@ def stage_roofline(cur, stages, steps_profiled, b, o, schedule):
     return roof, sections, stage_ms
 
 
+# Source files of each stage's kernels: a stage's measured traffic is used
+# only while the hash of these files matches the one stored with it.
+_FFT_SRC = ["fft.hip", "fft_tile.h"]
+STAGE_SOURCES = {
+    "fft_first": _FFT_SRC, "fft_mid": _FFT_SRC, "fft_last": _FFT_SRC,
+    "solve": ["solve.hip", "solve_bin.h"],
+    "spread": ["spread.hip", "spread_tile.h", "es_kernel.h"],
+    "persistent": ["persist.hip", "fft_tile.h", "spread_tile.h", "solve_bin.h"],
+}
+
+
+def stage_source_hash(stage):
+    """First 16 hex digits of the sha256 of the stage's kernel sources, or
+    None if the stage or a file is unknown."""
+    import hashlib
+    if stage not in STAGE_SOURCES:
+        return None
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES[stage]:
+        fp = os.path.join(ROOT, "paper_0901_1913_amd", "csrc", f)
+        if not os.path.isfile(fp):
+            return None
+        h.update(open(fp, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(name):
     """HBM bytes per launch of each stage from a committed rocprofv3 PMC
     summary (profiles/<name>_hbm_traffic.md), or {} if there is none, or None
     for a stage whose kernel source changed since the counters were taken."""
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.md")
     if not os.path.exists(path):
@@ -145,22 +170,10 @@ def measured_traffic(name):
     if not m:
         return {}
     meta = json.loads(m.group(1))
-    fft = ["fft.hip", "fft_tile.h"]
-    src = {"fft_first": fft, "fft_mid": fft, "fft_last": fft,
-           "solve": ["solve.hip", "solve_bin.h"],
-           "spread": ["spread.hip", "spread_tile.h", "es_kernel.h"],
-           "persistent": ["persist.hip", "fft_tile.h", "spread_tile.h", "solve_bin.h"]}
     out = {}
     for st, nbytes in meta.get("bytes_per_launch", {}).items():
-        h = hashlib.sha256()
-        ok = st in src
-        for f in src.get(st, []):
-            fp = os.path.join(ROOT, "paper_0901_1913_amd", "csrc", f)
-            if not os.path.isfile(fp):
-                ok = False
-                break
-            h.update(open(fp, "rb").read())
-        ok = ok and h.hexdigest()[:16] == meta.get("source_sha256_16", {}).get(st)
+        hx = stage_source_hash(st)
+        ok = hx is not None and hx == meta.get("source_sha256_16", {}).get(st)
         out[st] = int(nbytes) if ok else None
     return out
 
@@ -196,7 +209,10 @@ def oracle_pool(tasks):
     return res, time.perf_counter() - t0, cores
 
 
-def batch_sample(cur, seed=7, n_strat=32, bins_strat=96, bins_each=3):
+BINS_EACH = 30  # oracle bins on every curve of the batch sample
+
+
+def batch_sample(cur, seed=7, n_strat=32, bins_strat=96, bins_each=BINS_EACH):
     """The bounded oracle sample of the batch: 32 curves stratified by length
     and by signal / noise (8 length quartile x signal classes, 4 curves each)
     with bins_strat seeded random bins each, plus bins_each random bins on
@@ -264,9 +280,9 @@ _ORACLE_CACHE = {}
 
 
 def workload_line(name, steps, warmup, precision=None, parity_bins=256, seed=11,
-                  extra_bins=None):
-    """Timing (autotuned), stage split, roofline and oracle parity on sampled
-    bins of one single-curve workload."""
+                  extra_bins=None, schedule=None, tune_cache=None):
+    """Timing (autotuned, or on the given schedule), stage split, roofline and
+    oracle parity on sampled bins of one single-curve workload."""
     import torch
     from paper_0901_1913_amd import fchi2 as F
     from paper_0901_1913_amd import synth
@@ -280,7 +296,10 @@ def workload_line(name, steps, warmup, precision=None, parity_bins=256, seed=11,
     plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=prec, graph=True)
     ws = plan.workspace()
     t0 = time.perf_counter()
-    schedule = plan.autotune(t, x, s)
+    if schedule is not None:
+        schedule = plan.set_schedule(schedule)
+    else:
+        schedule = plan.autotune(t, x, s, cache_path=tune_cache)
     tune_s = time.perf_counter() - t0
     d = torch.empty((1, cur.H, cur.n_freq), dtype=plan.out_dtype, device="cuda")
     c0 = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -293,6 +312,7 @@ def workload_line(name, steps, warmup, precision=None, parity_bins=256, seed=11,
                            want_flags=False)
     b, o = (4, 4) if prec == "mixed" else (8, 8)
     roof, sections, stage_ms = stage_roofline(cur, st, 2, b, o, schedule)
+    roof["traffic"] = measured_traffic(f"{name}_{prec}").get(roof["kernel"])
     units = cur.n_freq * cur.H
     # Parity on seeded bins (plus the caller's bins), oracle on all cores.
     rng = np.random.default_rng(seed)
@@ -516,6 +536,19 @@ def band_share_timing(steps, G=8):
     return out
 
 
+def calibration_copy(mib):
+    """One device copy of mib MiB: a kernel of known traffic against which the
+    HBM counters of a profiled run are scaled."""
+    import torch
+    nel = mib * (1 << 20) // 4
+    c_src = torch.ones(nel, dtype=torch.float32, device="cuda")
+    c_dst = torch.empty_like(c_src)
+    torch.cuda.synchronize()
+    c_dst.copy_(c_src)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {mib} MiB read + {mib} MiB written")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -529,7 +562,14 @@ def main(argv=None):
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the shared-alpha, variants and band-share sections")
     ap.add_argument("--tune-cache", default=None,
-                    help="autotuner cache file for the batched search")
+                    help="autotuner cache file (one file serves every workload)")
+    ap.add_argument("--schedule", default=None,
+                    help="JSON schedule as Plan.info() reports it: applied instead of "
+                         "autotuning (batched search, or the --workload-only line)")
+    ap.add_argument("--workload-only", default=None,
+                    choices=["plain", "long", "diff", "stress"],
+                    help="run only this workload's line and print it (for profiling; "
+                         "not the headline)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device copy of this many MiB (a known-size kernel "
                          "against which HBM counters are scaled)")
@@ -550,6 +590,14 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    sched_arg = json.loads(a.schedule) if a.schedule else None
+    if a.workload_only:
+        if a.calib_copy_mb > 0:
+            calibration_copy(a.calib_copy_mb)
+        line = workload_line(a.workload_only, a.steps, a.warmup, schedule=sched_arg,
+                             tune_cache=a.tune_cache)
+        print(json.dumps({"workload_only": line}), flush=True)
+        return 0
     cur = synth.make("batch")
     n_tot = int(cur.t.shape[0])
     log(f"batch: {cur.n_curves} curves, {n_tot} points, H={cur.H}, n_freq={cur.n_freq}")
@@ -560,20 +608,16 @@ def main(argv=None):
                   graph=True)
     ws = plan.workspace()
     t0 = time.perf_counter()
-    schedule = plan.autotune(t, x, s, cache_path=a.tune_cache)
+    if sched_arg is not None:
+        schedule = plan.set_schedule(sched_arg)
+    else:
+        schedule = plan.autotune(t, x, s, cache_path=a.tune_cache)
     torch.cuda.synchronize()
     log(f"batch autotuned in {time.perf_counter() - t0:.1f} s (not timed): {schedule}")
     dchi2 = torch.empty((cur.n_curves, cur.H, cur.n_freq), dtype=plan.out_dtype, device="cuda")
     chi2_0 = torch.empty(cur.n_curves, dtype=torch.float64, device="cuda")
     if a.calib_copy_mb > 0:
-        nel = a.calib_copy_mb * (1 << 20) // 4
-        c_src = torch.ones(nel, dtype=torch.float32, device="cuda")
-        c_dst = torch.empty_like(c_src)
-        torch.cuda.synchronize()
-        c_dst.copy_(c_src)
-        torch.cuda.synchronize()
-        log(f"calibration copy: {a.calib_copy_mb} MiB read + {a.calib_copy_mb} MiB written")
-        del c_src, c_dst
+        calibration_copy(a.calib_copy_mb)
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     units = cur.n_curves * cur.n_freq * cur.H
@@ -609,7 +653,7 @@ def main(argv=None):
         ms_top = e0.elapsed_time(e1) / a.steps
         log(f"fused top-{K}: {ms_top:.3f} ms/step")
     roof, sections, stage_ms = stage_roofline(cur, st, 1, 4, 4, schedule)
-    roof["traffic"] = measured_traffic("batch").get(roof["kernel"])
+    roof["traffic"] = measured_traffic("batch_mixed").get(roof["kernel"])
     out = {
         "metric": METRIC, "value": round(units / (ms_step * 1e-3), 1), "unit": "freq*H/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
@@ -664,7 +708,7 @@ def main(argv=None):
             "value": round(v_cpu, 2), "unit": "freq*H/s", "cores": cores, "kind": "oracle",
             "sample": (f"{nb} bins (all H'=1..{cur.H}) of the batch workload: {len(strat)} "
                        f"curves stratified by length quartile and signal/noise with 96 "
-                       f"seeded bins each, plus 3 seeded bins on every curve; "
+                       f"seeded bins each, plus {BINS_EACH} seeded bins on every curve; "
                        f"{el:.1f} s wall"),
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "one_core_value": round(one, 2),
@@ -679,13 +723,15 @@ def main(argv=None):
         wl = {}
         k0 = int(round(2 ** 14 / 10.0 / 2.37))
         wl["plain_fp64"] = workload_line("plain", a.steps, a.warmup,
-                                         extra_bins=np.arange(k0 - 4, k0 + 5))
-        wl["long_mixed"] = workload_line("long", a.steps, a.warmup)
+                                         extra_bins=np.arange(k0 - 4, k0 + 5),
+                                         tune_cache=a.tune_cache)
+        wl["long_mixed"] = workload_line("long", a.steps, a.warmup, tune_cache=a.tune_cache)
         wl["diff"] = gradient_timing(a.steps)
-        wl["stress_mixed"] = workload_line("stress", max(3, a.steps // 2), 2, parity_bins=192)
+        wl["stress_mixed"] = workload_line("stress", max(3, a.steps // 2), 2, parity_bins=192,
+                                           tune_cache=a.tune_cache)
         torch.cuda.empty_cache()
         wl["stress_fp64"] = workload_line("stress", max(3, a.steps // 2), 2, precision="fp64",
-                                          parity_bins=192)
+                                          parity_bins=192, tune_cache=a.tune_cache)
         out["workloads"] = wl
     if not a.no_extras:
         torch.cuda.empty_cache()

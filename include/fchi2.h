@@ -535,6 +535,19 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
  */
 fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n);
 
+/*
+ * Apply a schedule in the layout fchi2_plan_info reports (n >= 14: FFT
+ * passes, log2 radices, log2 spreading tile, curves per wave, -, log2 FFT
+ * tiles, fused, persistent; info[7] is ignored) without timing anything, e.g.
+ * one an earlier fchi2_autotune chose, to reproduce a run.  The split must be
+ * one of the autotuner's candidates for the plan.  Like fchi2_autotune it
+ * ends the state a backward call would read.
+ * Errors: FCHI2_ERR_ARG (NULL, n, tile, wave, flags), FCHI2_ERR_UNSUPPORTED
+ * (a split the plan does not build, fused band plan, persistent schedule the
+ * persistent search does not take).
+ */
+fchi2_status_t fchi2_plan_set_schedule(fchi2_plan_t plan, const int32_t* info, int32_t n);
+
 /* Free the plan and its device tables (no-op for NULL). */
 void fchi2_destroy(fchi2_plan_t plan);
 

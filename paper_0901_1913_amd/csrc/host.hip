@@ -1643,6 +1643,43 @@ fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n) {
   return FCHI2_OK;
 }
 
+fchi2_status_t fchi2_plan_set_schedule(fchi2_plan_t plan, const int32_t* info, int32_t n) {
+  g_err.clear();
+  if (!plan || !info || n < 14) return fail(FCHI2_ERR_ARG, "plan/info NULL or n < 14");
+  fchi2_plan_s* pl = plan;
+  const int np = info[0];
+  const int tile = info[5], wave = info[6], fz = info[12], ps = info[13];
+  if (tile < 10 || tile > 13) return fail(FCHI2_ERR_ARG, "spreading tile must be 2^10..2^13");
+  if (wave < 1 || wave > pl->wave_max)
+    return fail(FCHI2_ERR_ARG, "curves per wave must be in 1..%d", pl->wave_max);
+  if ((fz != 0 && fz != 1) || (ps != 0 && ps != 1))
+    return fail(FCHI2_ERR_ARG, "fused and persistent entries must be 0 or 1");
+  if (fz == 1 && pl->g.band) return fail(FCHI2_ERR_UNSUPPORTED, "band plans are not fused");
+  const FftPlan* found = nullptr;
+  const std::vector<FftPlan> splits = fft_splits(pl->fp.logL, pl->fp64);
+  for (const FftPlan& f : splits) {
+    bool same = f.np == np;
+    for (int q = 1; q <= np && same; ++q)
+      same = f.logn[q] == info[q] && f.le[q] == info[7 + q];
+    if (same) found = &f;
+  }
+  if (!found) return fail(FCHI2_ERR_UNSUPPORTED, "not one of the plan's FFT schedules");
+  if (ps == 1 && !persist_ok(pl, *found, tile))
+    return fail(FCHI2_ERR_UNSUPPORTED, "the persistent search does not take this schedule");
+  if (pl->gexec) {
+    (void)hipGraphExecDestroy(pl->gexec);
+    pl->gexec = nullptr;
+  }
+  pl->log_tile = tile;
+  pl->wave = wave;
+  pl->fused = fz;
+  pl->persist = ps;
+  apply_fft_plan(pl, *found);
+  pl->last_ws = nullptr;
+  ++pl->gen;
+  return FCHI2_OK;
+}
+
 void fchi2_destroy(fchi2_plan_t plan) {
   if (!plan) return;
   for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);

@@ -37,6 +37,7 @@ EXPORTS = (
     "fchi2_search_multi_workspace_bytes", "fchi2_search_multi", "fchi2_detrend",
     "fchi2_autotune_multi", "fchi2_search_generation", "fchi2_backward_at",
     "fchi2_auto_n_freq", "fchi2_plan_n_freq", "fchi2_search_noalloc", "fchi2_search_coeffs",
+    "fchi2_plan_set_schedule",
 )
 PROF_STAGES = ("moments", "spread", "fft_first", "fft_mid", "fft_last", "solve",
                "bwd_solve", "bwd_fft", "bwd_gather", "bwd_final", "top_merge",
@@ -144,6 +145,8 @@ def lib() -> ctypes.CDLL:
     L.fchi2_autotune.restype = ctypes.c_int
     L.fchi2_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), i32]
     L.fchi2_plan_info.restype = ctypes.c_int
+    L.fchi2_plan_set_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), i32]
+    L.fchi2_plan_set_schedule.restype = ctypes.c_int
     L.fchi2_search_top_workspace_bytes.argtypes = [vp, i32]
     L.fchi2_search_top_workspace_bytes.restype = sz
     L.fchi2_search_top.argtypes = [vp, vp, vp, vp, vp, sz, i32, i64, i32, vp,
@@ -586,6 +589,28 @@ class Plan:
                 "spread_tile": 1 << int(arr[5]), "curves_per_wave": int(arr[6]),
                 "kernel_width": int(arr[7]), "fused_spread": bool(arr[12]),
                 "persistent": bool(arr[13])}
+
+    def set_schedule(self, schedule: dict) -> dict:
+        """Apply a schedule as info() reports it (FFT radices and tiles,
+        spreading tile, curves per wave, fused, persistent) without timing."""
+        arr = (ctypes.c_int32 * 14)()
+        ln = list(schedule["fft_log_radices"])
+        le = list(schedule["fft_log_tiles"])
+        if len(ln) != len(le) or not 1 <= len(ln) <= 4:
+            raise ValueError("fft_log_radices and fft_log_tiles must have 1..4 equal entries")
+        tile = int(schedule["spread_tile"])
+        if tile <= 0 or tile & (tile - 1):
+            raise ValueError("spread_tile must be a power of two")
+        arr[0] = len(ln)
+        for q, (a, b) in enumerate(zip(ln, le), 1):
+            arr[q] = int(a)
+            arr[7 + q] = int(b)
+        arr[5] = tile.bit_length() - 1
+        arr[6] = int(schedule["curves_per_wave"])
+        arr[12] = 1 if schedule.get("fused_spread") else 0
+        arr[13] = 1 if schedule.get("persistent") else 0
+        _check(lib().fchi2_plan_set_schedule(self._h, arr, 14))
+        return self.info()
 
     def profile(self, enable: bool = True):
         """Start (or stop) recording HIP event pairs around every launch."""

@@ -87,6 +87,8 @@ def test_null_arguments():
                                  None) == F.ERR_ARG
     assert L.fchi2_autotune(None, None, None, None, None, 0, None, None, None) == F.ERR_ARG
     assert L.fchi2_plan_info(None, None, 8) == F.ERR_ARG
+    arr = (ctypes.c_int32 * 14)()
+    assert L.fchi2_plan_set_schedule(None, arr, 14) == F.ERR_ARG
     assert L.fchi2_profile(None, 1) == F.ERR_ARG
     assert L.fchi2_profile_read(None, None, None) == F.ERR_ARG
     assert L.fchi2_workspace_bytes(None) == 0

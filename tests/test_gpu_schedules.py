@@ -116,3 +116,30 @@ def test_tile_size_changes_no_bit_forward_or_adjoint(tmp_path):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert torch.equal(a, b)
+
+
+def test_set_schedule_reproduces_the_tuned_plan():
+    """set_schedule applies a schedule as info() reports it: same results bit
+    for bit as the tuned plan; schedules the plan does not build are refused."""
+    import torch
+    cur = synth.make("batch", n_curves=12, n_freq=2 ** 16, f_max=10.0, n_lo=100, n_hi=3000)
+    t, x, s = to_dev(cur)
+    note("set_schedule: tuned plan")
+    a = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed")
+    info = a.autotune(t, x, s)
+    da, ca, fa = a.search(t, x, s)
+    torch.cuda.synchronize()
+    note(f"set_schedule: {info}")
+    b = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed")
+    assert b.set_schedule(info) == info
+    db, cb, fb = b.search(t, x, s)
+    torch.cuda.synchronize()
+    assert torch.equal(da, db) and torch.equal(ca, cb) and torch.equal(fa, fb)
+    for bad in (dict(info, fft_log_radices=[5, 5, 5, 3], fft_log_tiles=[12] * 4),
+                dict(info, fft_log_tiles=[11] * len(info["fft_log_tiles"])),
+                dict(info, curves_per_wave=10 ** 6), dict(info, spread_tile=512)):
+        with pytest.raises(F.FChi2Error):
+            b.set_schedule(bad)
+    assert b.info() == info
+    a.close()
+    b.close()
