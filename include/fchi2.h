@@ -508,8 +508,9 @@ fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* 
  * (the FFT digit splits with the fewest passes and the most balanced splits
  * with one pass more, for FP32 grids each on FFT tiles of 4096 or 8192
  * elements per pass, spreading tiles of 1024 to 8192 cells or, outside band
- * plans, the spreading fused into the first FFT pass, and waves of wave_max,
- * wave_max/2, wave_max/4 curves) with HIP
+ * plans, the spreading fused into the first FFT pass, waves of wave_max,
+ * wave_max/2, wave_max/4 curves, and for batches that fill the device the
+ * persistent search) with HIP
  * events on `stream` (two timed runs each after a warm-up, then the three
  * fastest five more times each, in turns), keeps the fastest in the plan,
  * and appends it to the
