@@ -182,8 +182,10 @@ int64_t fchi2_auto_n_freq(int32_t H, double f_max, double oversampling, double s
  * L = 4 n_freq cells per harmonic grid, 2 n_freq in a band plan; Section 3b's
  * zero-padded arrays), the FFT pass split and the spreading kernel, and
  * builds its device tables (twiddles, deconvolution) on `stream`, waiting for
- * them.  Allocates device memory for those tables (owned by the plan).  On
- * success *out receives the plan.
+ * them.  Allocates device memory for those tables (owned by the plan); a
+ * plan of several curves (not a band plan) also creates a second stream of
+ * default priority and a few events (owned by the plan) for the overlapped
+ * wave schedule of fchi2_search.  On success *out receives the plan.
  * The grids are periodic: when 2H * span * f_max / n_freq exceeds 1 the
  * harmonic phases wrap around them, which is handled (the transforms at
  * integer bins are unchanged by whole periods); the tile tables cover enough
@@ -215,6 +217,12 @@ int64_t fchi2_total_points(fchi2_plan_t plan);
  *  chi2_0       device FP64 [n_curves] or NULL
  *  flags        device uint8 [n_curves][n_freq] (FCHI2_BIN_* / FCHI2_CURVE_*)
  *               or NULL
+ * With waves of at most half the buffers' capacity (a tuned or set
+ * schedule), the spreading of the next wave runs on the plan's second stream
+ * while `stream` runs the current wave's FFT passes and solve; the two are
+ * ordered by events and all of it is joined back into `stream` (stream
+ * order and graph capture behave as for one stream).  The results are the
+ * same bit for bit.
  * Errors: FCHI2_ERR_ARG (NULL plan/pointer, misaligned or small workspace),
  * FCHI2_ERR_HIP.
  */
@@ -509,8 +517,10 @@ fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* 
  * with one pass more, for FP32 grids each on FFT tiles of 4096 or 8192
  * elements per pass, spreading tiles of 1024 to 8192 cells or, outside band
  * plans, the spreading fused into the first FFT pass, waves of wave_max,
- * wave_max/2, wave_max/4 curves, and for batches that fill the device the
- * persistent search) with HIP
+ * wave_max/2, /4, /6, /8, /10, /12 curves with the last FFT pass and the
+ * solve on whole or half waves, and for batches that fill the device the
+ * persistent search; splits and tiles are ranked on the largest wave, wave
+ * sizes for the three best of those) with HIP
  * events on `stream` (two timed runs each after a warm-up, then the three
  * fastest five more times each, in turns), keeps the fastest in the plan,
  * and appends it to the
@@ -532,14 +542,17 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
  * per wave, info[7] = kernel width, and with n >= 12 info[8..11] = log2 FFT
  * tile elements of passes 1..4 (0 if unused), with n >= 13 info[12] = 1 if
  * the spreading runs inside the first FFT pass, with n >= 14 info[13] = 1 if
- * searches run as one persistent launch.  n must be >= 8.
+ * searches run as one persistent launch, with n >= 15 info[14] = curves per
+ * launch of the last FFT pass and the solve (0: the whole wave).  n must be
+ * >= 8.
  */
 fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n);
 
 /*
  * Apply a schedule in the layout fchi2_plan_info reports (n >= 14: FFT
  * passes, log2 radices, log2 spreading tile, curves per wave, -, log2 FFT
- * tiles, fused, persistent; info[7] is ignored) without timing anything, e.g.
+ * tiles, fused, persistent, and with n >= 15 the last pass's sub-wave, else
+ * 0; info[7] is ignored) without timing anything, e.g.
  * one an earlier fchi2_autotune chose, to reproduce a run.  The split must be
  * one of the autotuner's candidates for the plan.  Like fchi2_autotune it
  * ends the state a backward call would read.

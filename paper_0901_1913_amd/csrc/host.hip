@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -276,9 +277,14 @@ std::vector<FftPlan> fft_splits(int logL, bool fp64) {
     out.push_back(f);
   };
   for (const FftPlan& f : base) {
-    for (int v = 0; v < 3; ++v) {  // all 2^12 tiles, all 2^13, first pass 2^12 and the rest 2^13
+    // All 2^12 tiles; all 2^13; first pass 2^12 and the rest 2^13; first pass
+    // 2^13 and the rest 2^12.
+    for (int v = 0; v < 4; ++v) {
       FftPlan g = f;
-      for (int q = 1; q <= g.np; ++q) g.le[q] = (v == 0 || (v == 2 && q == g.np)) ? 12 : 13;
+      for (int q = 1; q <= g.np; ++q) {
+        const bool first = q == g.np;
+        g.le[q] = (v == 1 || (v == 2 && !first) || (v == 3 && first)) ? 13 : 12;
+      }
       add(g);
     }
   }
@@ -302,6 +308,15 @@ struct fchi2_plan_s {
   // queue by n_slots workgroups, each with a slot of the workspace (its
   // grids, spectra and tile table) at off_gA + slot * slot_bytes.
   int persist = 0;
+  // Curves per launch of the last FFT pass and the solve (0: the whole wave).
+  int solve_sub = 0;
+  // Overlap of the next wave's spreading with this wave's FFT passes and
+  // solve: a second stream (default priority) and the events that order the
+  // two; used for waves of at most wave_max / 2 curves, whose two spread
+  // grids and tile tables fit in the one-wave buffers.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_start = nullptr, ev_spread[2] = {nullptr, nullptr},
+             ev_first[2] = {nullptr, nullptr};
   int n_slots = 0;
   int n_slots_device = 0;  // workgroups resident on the whole device
   size_t slot_bytes = 0, slot_gB = 0, slot_zc = 0, slot_tb = 0;
@@ -379,11 +394,21 @@ hipError_t prof_mark(fchi2_plan_s* pl, int stage, hipStream_t st) {
 // fused_pts: the forward first pass spreads these points (t, x, sigma) in
 // its tiles instead of reading gA (null: read the spread grid), finding them
 // through the tile table fused_tb (tiles of 2^kFusedTbLog cells).
+// after_last (forward, may be null): called with (offset, count) after the
+// last pass has written the spectra of curves [curve0 + offset, + count);
+// with 0 < sub < nw the last pass runs in sub-waves of sub curves, each
+// followed by its call, so the spectra a call reads were just written.
+// after_first (may be null): called once the first pass (the last reader of
+// gA) is enqueued.
+using AfterLast = std::function<fchi2_status_t(int, int)>;
+using AfterFirst = std::function<fchi2_status_t()>;
 fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void* zc,
                            const Moments* mom, int curve0, int nw, hipStream_t st,
                            const Geom* geom = nullptr,
                            const double* const* fused_pts = nullptr,
-                           const int32_t* fused_tb = nullptr) {
+                           const int32_t* fused_tb = nullptr, int sub = 0,
+                           const AfterLast* after_last = nullptr,
+                           const AfterFirst* after_first = nullptr) {
   const Geom& g = geom ? *geom : pl->g;
   const FftPlan& fp = pl->fp;
   FftPassArgs a{};
@@ -402,7 +427,11 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
                                    pl->d_tw_small, nw, 1, st);
     if (e != hipSuccess) return hip_fail(e, "fft single pass");
     PROF_END();
-    return FCHI2_OK;
+    if (after_first) {
+      fchi2_status_t r = (*after_first)();
+      if (r != FCHI2_OK) return r;
+    }
+    return after_last ? (*after_last)(0, nw) : FCHI2_OK;
   }
   for (int q = fp.np; q >= 1; --q) {
     a.q = q;
@@ -424,11 +453,31 @@ fchi2_status_t enqueue_fft(fchi2_plan_s* pl, int mode, void* gA, void* gB, void*
                       : a.kind == PASS_FIRST ? FCHI2_PROF_FFT_FIRST
                       : a.kind == PASS_MID   ? FCHI2_PROF_FFT_MID
                                              : FCHI2_PROF_FFT_LAST;
-    PROF_BEGIN(stage);
-    hipError_t e = launch_fft_pass(pl->fp64, a, logn, logt, in, out, mom, g, pl->d_tw_stage,
-                                   pl->d_tw_small, nw, ncols, st);
-    if (e != hipSuccess) return hip_fail(e, "fft pass");
-    PROF_END();
+    const bool split = q == 1 && mode == MODE_FWD && sub > 0 && sub < nw;
+    const int step = split ? sub : nw;
+    const size_t grid_curve = (size_t)g.P * (size_t)g.L * pl->elem;
+    const size_t zc_curve = (size_t)g.P * 2 * (size_t)g.n_freq * pl->elem;
+    for (int off = 0; off < nw; off += step) {
+      const int n = (nw - off) < step ? (nw - off) : step;
+      FftPassArgs b = a;
+      b.curve0 = curve0 + off;
+      if (zc) b.zc = (char*)zc + (size_t)off * zc_curve;
+      PROF_BEGIN(stage);
+      hipError_t e = launch_fft_pass(pl->fp64, b, logn, logt,
+                                     (const char*)in + (size_t)off * grid_curve,
+                                     (char*)out + (size_t)off * grid_curve, mom, g,
+                                     pl->d_tw_stage, pl->d_tw_small, n, ncols, st);
+      if (e != hipSuccess) return hip_fail(e, "fft pass");
+      PROF_END();
+      if (q == 1 && after_last) {
+        fchi2_status_t r = (*after_last)(off, n);
+        if (r != FCHI2_OK) return r;
+      }
+    }
+    if (q == fp.np && after_first) {
+      fchi2_status_t r = (*after_first)();
+      if (r != FCHI2_OK) return r;
+    }
   }
   return FCHI2_OK;
 }
@@ -506,6 +555,76 @@ fchi2_status_t enqueue_persistent(fchi2_plan_s* pl, int cbeg, int cend, const do
   return FCHI2_OK;
 }
 
+// Whether a search of n curves runs the overlapped wave schedule: staged
+// (not fused, not persistent), at least two waves, and waves of at most half
+// the buffers' capacity (two spread grids and tables fit).
+bool use_overlap(const fchi2_plan_s* pl, int n) {
+  return pl->side && !use_fused(pl) && !pl->g.band && n > pl->wave &&
+         2 * pl->wave <= pl->wave_max;
+}
+
+// The forward chain with the spreading of wave i + 1 on the side stream while
+// the main stream runs wave i's FFT passes and solve.  Wave i spreads into
+// grid A buffer i % 2 (halves of the grid A region) with table i % 2 (halves
+// of the table region); the side stream waits for the first pass that last
+// read that buffer (wave i - 2), the main stream for wave i's spreading.
+// Every kernel is the staged search's on the same curves, so the results are
+// identical bit for bit.  Every piece of side-stream work is waited on by the
+// main stream before the call returns to it, so graph capture joins.
+fchi2_status_t enqueue_search_overlap(fchi2_plan_s* pl, int cbeg, int cend, const double* t,
+                                      const double* x, const double* sigma, char* ws,
+                                      void* dchi2, uint8_t* flags, hipStream_t st,
+                                      void* coef) {
+  Moments* mom = (Moments*)(ws + pl->off_mom);
+  const bool keep = pl->desc.flags & FCHI2_KEEP_FOR_BACKWARD;
+  const size_t zc_curve = (size_t)pl->g.P * 2 * pl->g.n_freq * pl->elem;
+  const size_t grid_curve = (size_t)pl->g.P * (size_t)pl->g.L * pl->elem;
+  const size_t tb_half = align256(tile_bounds_bytes(pl->g, pl->log_tile, pl->wave));
+  hipStream_t sd = pl->side;
+  hipError_t e = hipEventRecord(pl->ev_start, st);  // moments are done before any spreading
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if ((e = hipStreamWaitEvent(sd, pl->ev_start, 0)) != hipSuccess)
+    return hip_fail(e, "hipStreamWaitEvent");
+  int i = 0;
+  for (int c0 = cbeg; c0 < cend; c0 += pl->wave, ++i) {
+    const int nw = (cend - c0) < pl->wave ? (cend - c0) : pl->wave;
+    const int b = i & 1;
+    char* gA = ws + pl->off_gA + (size_t)b * grid_curve * pl->wave;
+    int32_t* tb = (int32_t*)(ws + pl->off_tb + (size_t)b * tb_half);
+    void* gB = ws + pl->off_gB;
+    void* zc = ws + pl->off_zc + (keep ? (size_t)c0 * zc_curve : 0);
+    if (i >= 2 && (e = hipStreamWaitEvent(sd, pl->ev_first[b], 0)) != hipSuccess)
+      return hip_fail(e, "hipStreamWaitEvent");
+    if ((e = prof_mark(pl, FCHI2_PROF_SPREAD, sd)) != hipSuccess)
+      return hip_fail(e, "profiling event");
+    e = launch_spread(pl->fp64, t, x, sigma, mom, pl->g, c0, nw, pl->max_n, tb, gA,
+                      pl->log_tile, sd);
+    if (e != hipSuccess) return hip_fail(e, "spread");
+    if ((e = prof_mark(pl, -1, sd)) != hipSuccess) return hip_fail(e, "profiling event");
+    if ((e = hipEventRecord(pl->ev_spread[b], sd)) != hipSuccess)
+      return hip_fail(e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(st, pl->ev_spread[b], 0)) != hipSuccess)
+      return hip_fail(e, "hipStreamWaitEvent");
+    const AfterLast solve = [&](int off, int n) -> fchi2_status_t {
+      PROF_BEGIN(FCHI2_PROF_SOLVE);
+      hipError_t es = launch_solve(pl->fp64, (char*)zc + (size_t)off * zc_curve, pl->d_D, mom,
+                                   pl->g, c0 + off, n, pl->eps_piv, dchi2, flags, st, coef,
+                                   (pl->desc.flags & FCHI2_WIDE_SOLVE) != 0);
+      if (es != hipSuccess) return hip_fail(es, "solve");
+      PROF_END();
+      return FCHI2_OK;
+    };
+    const AfterFirst first_done = [&]() -> fchi2_status_t {
+      hipError_t ef = hipEventRecord(pl->ev_first[b], st);
+      return ef == hipSuccess ? FCHI2_OK : hip_fail(ef, "hipEventRecord");
+    };
+    fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st, nullptr, nullptr,
+                                   nullptr, pl->solve_sub, &solve, &first_done);
+    if (s != FCHI2_OK) return s;
+  }
+  return FCHI2_OK;
+}
+
 // The whole forward chain for curves [cbeg, cend), in waves of pl->wave.
 fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double* t,
                               const double* x, const double* sigma, char* ws, void* dchi2,
@@ -520,6 +639,8 @@ fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double
   PROF_END();
   if (use_persist(pl) && !coef)
     return enqueue_persistent(pl, cbeg, cend, t, x, sigma, ws, dchi2, flags, st);
+  if (use_overlap(pl, cend - cbeg))
+    return enqueue_search_overlap(pl, cbeg, cend, t, x, sigma, ws, dchi2, flags, st, coef);
   const bool keep = pl->desc.flags & FCHI2_KEEP_FOR_BACKWARD;
   const size_t zc_curve = (size_t)pl->g.P * 2 * pl->g.n_freq * pl->elem;
   for (int c0 = cbeg; c0 < cend; c0 += pl->wave) {
@@ -537,14 +658,18 @@ fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double
       e = launch_tile_bounds(t, mom, pl->g, c0, nw, pl->max_n, tb, kFusedTbLog, st);
     if (e != hipSuccess) return hip_fail(e, "spread");
     PROF_END();
+    const AfterLast solve = [&](int off, int n) -> fchi2_status_t {
+      PROF_BEGIN(FCHI2_PROF_SOLVE);
+      hipError_t es = launch_solve(pl->fp64, (char*)zc + (size_t)off * zc_curve, pl->d_D, mom,
+                                   pl->g, c0 + off, n, pl->eps_piv, dchi2, flags, st, coef,
+                                   (pl->desc.flags & FCHI2_WIDE_SOLVE) != 0);
+      if (es != hipSuccess) return hip_fail(es, "solve");
+      PROF_END();
+      return FCHI2_OK;
+    };
     fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st, nullptr,
-                                   use_fused(pl) ? pts : nullptr, tb);
+                                   use_fused(pl) ? pts : nullptr, tb, pl->solve_sub, &solve);
     if (s != FCHI2_OK) return s;
-    PROF_BEGIN(FCHI2_PROF_SOLVE);
-    e = launch_solve(pl->fp64, zc, pl->d_D, mom, pl->g, c0, nw, pl->eps_piv, dchi2, flags, st,
-                     coef, (pl->desc.flags & FCHI2_WIDE_SOLVE) != 0);
-    if (e != hipSuccess) return hip_fail(e, "solve");
-    PROF_END();
   }
   return FCHI2_OK;
 }
@@ -706,22 +831,27 @@ fchi2_status_t check_ws(fchi2_plan_s* pl, void* ws, size_t bytes) {
   return FCHI2_OK;
 }
 
-// Time every (FFT split, spreading tile, wave) candidate with `run` (3 runs,
-// the first a warm-up, keep the faster of the other two), then time the three
-// fastest again, in turns, five times each and return the one with the lowest
-// time: the first round ranks, the second decides between close candidates
-// whose order one noisy measurement could swap.  The plan is left on the last
-// candidate tried.
+// Schedule search with `run`.  Stage 1 times every (FFT split, spreading
+// tile) on the largest wave (plus the fused first pass and the persistent
+// search where allowed); stage 2 times, for the three fastest of stage 1,
+// every wave size, each with the last pass and solve run on the whole wave
+// or on half-waves (allow_sub).  Each candidate runs 3 times (the first a
+// warm-up, the faster of the other two kept); then the three fastest of all
+// run again, in turns, five times each, and the one with the lowest time is
+// returned: the first rounds rank, the last decides between close candidates
+// whose order one noisy measurement could swap.  The plan is left on the
+// last candidate tried.
+struct TuneCand {
+  FftPlan f;
+  int tile, wave, fused, persist, sub;
+  float ms;
+};
+
 template <typename Run>
 fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
                          const std::vector<int>& waves, bool allow_fused, bool allow_persist,
-                         Run run, hipStream_t st, float& best_ms, FftPlan& best_f,
-                         int& best_tile, int& best_wave, int& best_fused, int& best_persist) {
-  struct Cand {
-    FftPlan f;
-    int tile, wave, fused, persist;
-    float ms;
-  };
+                         bool allow_sub, Run run, hipStream_t st, float& best_ms,
+                         TuneCand& best) {
   hipEvent_t e0, e1;
   hipError_t ce = hipEventCreate(&e0);
   if (ce != hipSuccess) return hip_fail(ce, "hipEventCreate");
@@ -732,11 +862,12 @@ fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
   }
   fchi2_status_t res = FCHI2_OK;
   // One timed run of candidate c into ms.
-  auto time_one = [&](const Cand& c, float& ms) {
+  auto time_one = [&](const TuneCand& c, float& ms) {
     pl->log_tile = c.tile;
     pl->wave = c.wave;
     pl->fused = c.fused;
     pl->persist = c.persist;
+    pl->solve_sub = c.sub;
     apply_fft_plan(pl, c.f);
     hipError_t e = hipEventRecord(e0, st);
     if (e == hipSuccess) res = run();
@@ -746,29 +877,52 @@ fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
     if (e == hipSuccess && res == FCHI2_OK) e = hipEventElapsedTime(&ms, e0, e1);
     if (e != hipSuccess) res = hip_fail(e, "autotune timing");
   };
-  std::vector<Cand> cands;
-  for (const FftPlan& f : splits) {
-    for (int wave : waves) {
-      for (int tile : {10, 11, 12, 13}) cands.push_back(Cand{f, tile, wave, 0, 0, 1e30f});
-      // The fused schedule has no spreading tile.
-      if (allow_fused && f.np >= 2) cands.push_back(Cand{f, 10, wave, 1, 0, 1e30f});
+  auto time_all = [&](std::vector<TuneCand>& cs) {
+    for (TuneCand& c : cs) {
+      for (int rep = 0; rep < 3 && res == FCHI2_OK; ++rep) {
+        float ms = 0.f;
+        time_one(c, ms);
+        if (rep > 0 && res == FCHI2_OK && ms < c.ms) c.ms = ms;  // first run warms up
+      }
+      if (res != FCHI2_OK) return;
     }
+  };
+  auto by_time = [](const TuneCand& a, const TuneCand& b) { return a.ms < b.ms; };
+  std::vector<TuneCand> cands;
+  const int w0 = waves[0];
+  for (const FftPlan& f : splits) {
+    for (int tile : {10, 11, 12, 13}) cands.push_back(TuneCand{f, tile, w0, 0, 0, 0, 1e30f});
+    // The fused schedule has no spreading tile.
+    if (allow_fused && f.np >= 2) cands.push_back(TuneCand{f, 10, w0, 1, 0, 0, 1e30f});
     // The persistent search has no waves.
     for (int tile : {10, 11})
       if (allow_persist && persist_ok(pl, f, tile) && persist_worth_timing(pl))
-        cands.push_back(Cand{f, tile, waves[0], 0, 1, 1e30f});
+        cands.push_back(TuneCand{f, tile, w0, 0, 1, 0, 1e30f});
   }
-  for (Cand& c : cands) {
-    for (int rep = 0; rep < 3 && res == FCHI2_OK; ++rep) {
-      float ms = 0.f;
-      time_one(c, ms);
-      if (rep > 0 && res == FCHI2_OK && ms < c.ms) c.ms = ms;  // first run warms up
+  time_all(cands);
+  if (res == FCHI2_OK && !cands.empty()) {
+    std::stable_sort(cands.begin(), cands.end(), by_time);
+    std::vector<TuneCand> more;
+    int taken = 0;
+    for (size_t i = 0; i < cands.size() && taken < 3; ++i) {
+      if (cands[i].persist) continue;
+      ++taken;
+      for (int wave : waves)
+        for (int half = 0; half <= (allow_sub ? 1 : 0); ++half) {
+          TuneCand c = cands[i];
+          c.wave = wave;
+          c.sub = half ? wave / 2 : 0;
+          c.ms = 1e30f;
+          if (half && c.sub < 1) continue;
+          if (wave == w0 && !half) continue;  // timed in stage 1
+          more.push_back(c);
+        }
     }
-    if (res != FCHI2_OK) break;
+    time_all(more);
+    cands.insert(cands.end(), more.begin(), more.end());
   }
   if (res == FCHI2_OK && !cands.empty()) {
-    std::stable_sort(cands.begin(), cands.end(),
-                     [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+    std::stable_sort(cands.begin(), cands.end(), by_time);
     const size_t top = cands.size() < 3 ? cands.size() : 3;
     std::vector<float> again(top, 1e30f);
     for (int rep = 0; rep < 5 && res == FCHI2_OK; ++rep)
@@ -783,17 +937,22 @@ fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
         if (again[i] < again[bi]) bi = i;
       if (again[bi] < best_ms) {
         best_ms = again[bi];
-        best_f = cands[bi].f;
-        best_tile = cands[bi].tile;
-        best_wave = cands[bi].wave;
-        best_fused = cands[bi].fused;
-        best_persist = cands[bi].persist;
+        best = cands[bi];
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return res;
+}
+
+void apply_tuned(fchi2_plan_s* pl, const TuneCand& c) {
+  pl->log_tile = c.tile;
+  pl->wave = c.wave;
+  pl->fused = c.fused;
+  pl->persist = c.persist;
+  pl->solve_sub = c.sub;
+  apply_fft_plan(pl, c.f);
 }
 
 }  // namespace
@@ -1089,6 +1248,15 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   void* sp = nullptr;
   if ((e = scratch_address(&sp)) != hipSuccess)
     return cleanup_fail(hip_fail(e, "hipGetSymbolAddress(scratch)"));
+  // The spreading stream of the overlapped wave schedule (default priority).
+  if (d.n_curves > 1 && !g.band) {
+    if ((e = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking)) != hipSuccess)
+      return cleanup_fail(hip_fail(e, "hipStreamCreateWithFlags"));
+    for (hipEvent_t* ev : {&pl->ev_start, &pl->ev_spread[0], &pl->ev_spread[1], &pl->ev_first[0],
+                           &pl->ev_first[1]})
+      if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess)
+        return cleanup_fail(hip_fail(e, "hipEventCreateWithFlags"));
+  }
   *out = pl;
   return FCHI2_OK;
 }
@@ -1456,22 +1624,16 @@ fchi2_status_t fchi2_autotune_multi(fchi2_plan_t plan, const double* t, const do
   const bool prof = pl->prof;
   pl->prof = false;
   float best_ms = 1e30f;
-  FftPlan best_f = pl->fp;
-  int best_tile = pl->log_tile, best_wave = pl->wave, best_fused = pl->fused;
-  int best_persist = pl->persist;
+  TuneCand best{pl->fp, pl->log_tile, pl->wave, pl->fused, pl->persist, pl->solve_sub, 0.f};
   fchi2_status_t res = tune_loop(
-      pl, splits, waves, false, false,
+      pl, splits, waves, false, false, false,
       [&]() {
         return enqueue_multi(pl, multi_layout(pl, n_sources), t, sigma, x, scale, n_sources,
                              (char*)workspace, dchi2, nullptr, nullptr, st);
       },
-      st, best_ms, best_f, best_tile, best_wave, best_fused, best_persist);
+      st, best_ms, best);
   pl->prof = prof;
-  pl->log_tile = best_tile;
-  pl->wave = best_wave;
-  pl->fused = best_fused;
-  pl->persist = best_persist;
-  apply_fft_plan(pl, best_f);
+  apply_tuned(pl, best);
   pl->last_ws = nullptr;
   ++pl->gen;
   return res;
@@ -1568,19 +1730,23 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
         const char* tag = strstr(line, " | ");
         if (!tag || strncmp(line, key, strlen(key)) != 0 || line + strlen(key) != tag) continue;
         int np = 0, ln[kMaxPasses + 1] = {0}, le[kMaxPasses + 1] = {0}, tile = 0, wave = 0;
-        // Lines without the fused / persist fields name the staged schedule.
-        int fz = 0, ps = 0;
+        // Lines without the fused / persist / sub fields name the staged
+        // schedule on whole waves.
+        int fz = 0, ps = 0, sb = 0;
         if (sscanf(tag,
-                   " | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d fused=%d persist=%d",
+                   " | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d fused=%d persist=%d "
+                   "sub=%d",
                    &np, &ln[1], &ln[2], &ln[3], &ln[4], &le[1], &le[2], &le[3], &le[4], &tile,
-                   &wave, &fz, &ps) >= 11 &&
+                   &wave, &fz, &ps, &sb) >= 11 &&
             tile >= 10 && tile <= 13 && wave >= 1 && wave <= pl->wave_max &&
-            (fz == 0 || (fz == 1 && !pl->g.band)) && (ps == 0 || ps == 1)) {
+            (fz == 0 || (fz == 1 && !pl->g.band)) && (ps == 0 || ps == 1) && sb >= 0 &&
+            sb <= wave) {
           found = apply(ln, le, np, tile, wave);
           if (found && ps == 1 && !persist_ok(pl, pl->fp, tile)) found = false;
           if (found) {
             pl->fused = fz;
             pl->persist = ps;
+            pl->solve_sub = sb;
           }
         }
       }
@@ -1589,29 +1755,32 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
     }
   }
   // Time every candidate on the caller's data.
+  // Waves of wave_max, /2, /4, /6, /8, /10, /12 curves: smaller waves keep a
+  // wave's spectra (and part of its grids) in the 256 MB Infinity Cache
+  // between the pass that writes them and the kernel that reads them, and
+  // (at most half the buffers) overlap the next wave's spreading with the
+  // current wave's passes.
   std::vector<int> waves = {pl->wave_max};
-  for (int w = pl->wave_max / 2; w >= 1 && waves.size() < 3 && pl->desc.n_curves > 1; w /= 2)
-    waves.push_back(w);
+  if (pl->desc.n_curves > 1)
+    for (int div : {2, 4, 6, 8, 10, 12}) {
+      const int w = pl->wave_max / div;
+      if (w >= 1 && w != waves.back()) waves.push_back(w);
+    }
   const bool prof = pl->prof;
   pl->prof = false;
   float best_ms = 1e30f;
-  FftPlan best_f = pl->fp;
-  int best_tile = pl->log_tile, best_wave = pl->wave, best_fused = pl->fused;
-  int best_persist = pl->persist;
+  TuneCand best{pl->fp, pl->log_tile, pl->wave, pl->fused, pl->persist, pl->solve_sub, 0.f};
   const bool allow_fused = !pl->g.band;
   fchi2_status_t res = tune_loop(
-      pl, splits, waves, allow_fused, true,
+      pl, splits, waves, allow_fused, true, pl->desc.n_curves > 1,
       [&]() {
         return enqueue_search(pl, 0, pl->desc.n_curves, t, x, sigma, (char*)workspace, dchi2,
                               nullptr, nullptr, st);
       },
-      st, best_ms, best_f, best_tile, best_wave, best_fused, best_persist);
+      st, best_ms, best);
   pl->prof = prof;
-  pl->log_tile = best_tile;
-  pl->wave = best_wave;
-  pl->fused = best_fused;
-  pl->persist = best_persist;
-  apply_fft_plan(pl, best_f);
+  apply_tuned(pl, best);
+  const FftPlan& best_f = best.f;
   pl->last_ws = nullptr;
   ++pl->gen;
   if (res != FCHI2_OK) return res;
@@ -1619,10 +1788,10 @@ fchi2_status_t fchi2_autotune(fchi2_plan_t plan, const double* t, const double* 
     if (FILE* fh = fopen(cache_path, "a")) {
       fprintf(fh,
               "%s | np=%d fft=%d,%d,%d,%d le=%d,%d,%d,%d tile=%d wave=%d fused=%d persist=%d "
-              "ms=%.4f\n",
+              "sub=%d ms=%.4f\n",
               key, best_f.np, best_f.logn[1], best_f.logn[2], best_f.logn[3], best_f.logn[4],
-              best_f.le[1], best_f.le[2], best_f.le[3], best_f.le[4], best_tile, best_wave,
-              best_fused, best_persist, best_ms);
+              best_f.le[1], best_f.le[2], best_f.le[3], best_f.le[4], best.tile, best.wave,
+              best.fused, best.persist, best.sub, best_ms);
       fclose(fh);
     }
   }
@@ -1640,6 +1809,7 @@ fchi2_status_t fchi2_plan_info(fchi2_plan_t plan, int32_t* info, int32_t n) {
   for (int q = 1; q <= kMaxPasses && 7 + q < n; ++q) info[7 + q] = q <= plan->fp.np ? plan->fp.le[q] : 0;
   if (n > 12) info[12] = use_fused(plan) ? 1 : 0;
   if (n > 13) info[13] = use_persist(plan) ? 1 : 0;
+  if (n > 14) info[14] = plan->solve_sub;
   return FCHI2_OK;
 }
 
@@ -1670,10 +1840,13 @@ fchi2_status_t fchi2_plan_set_schedule(fchi2_plan_t plan, const int32_t* info, i
     (void)hipGraphExecDestroy(pl->gexec);
     pl->gexec = nullptr;
   }
+  const int sb = n > 14 ? info[14] : 0;
+  if (sb < 0 || sb > wave) return fail(FCHI2_ERR_ARG, "solve sub-wave must be in 0..wave");
   pl->log_tile = tile;
   pl->wave = wave;
   pl->fused = fz;
   pl->persist = ps;
+  pl->solve_sub = sb;
   apply_fft_plan(pl, *found);
   pl->last_ws = nullptr;
   ++pl->gen;
@@ -1689,6 +1862,10 @@ void fchi2_destroy(fchi2_plan_t plan) {
   if (plan->d_tw_small) (void)hipFree(plan->d_tw_small);
   if (plan->d_D) (void)hipFree(plan->d_D);
   if (plan->d_gl) (void)hipFree(plan->d_gl);
+  for (hipEvent_t e : {plan->ev_start, plan->ev_spread[0], plan->ev_spread[1], plan->ev_first[0],
+                       plan->ev_first[1]})
+    if (e) (void)hipEventDestroy(e);
+  if (plan->side) (void)hipStreamDestroy(plan->side);
   delete plan;
 }
 

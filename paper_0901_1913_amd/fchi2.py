@@ -581,19 +581,19 @@ class Plan:
 
     def info(self) -> dict:
         """The plan's schedule: FFT radices, spreading tile, wave, kernel width."""
-        arr = (ctypes.c_int32 * 14)()
-        _check(lib().fchi2_plan_info(self._h, arr, 14))
+        arr = (ctypes.c_int32 * 15)()
+        _check(lib().fchi2_plan_info(self._h, arr, 15))
         np_ = int(arr[0])
         return {"fft_log_radices": [int(arr[q]) for q in range(1, np_ + 1)],
                 "fft_log_tiles": [int(arr[7 + q]) for q in range(1, np_ + 1)],
                 "spread_tile": 1 << int(arr[5]), "curves_per_wave": int(arr[6]),
                 "kernel_width": int(arr[7]), "fused_spread": bool(arr[12]),
-                "persistent": bool(arr[13])}
+                "persistent": bool(arr[13]), "solve_sub_wave": int(arr[14])}
 
     def set_schedule(self, schedule: dict) -> dict:
         """Apply a schedule as info() reports it (FFT radices and tiles,
         spreading tile, curves per wave, fused, persistent) without timing."""
-        arr = (ctypes.c_int32 * 14)()
+        arr = (ctypes.c_int32 * 15)()
         ln = list(schedule["fft_log_radices"])
         le = list(schedule["fft_log_tiles"])
         if len(ln) != len(le) or not 1 <= len(ln) <= 4:
@@ -609,7 +609,8 @@ class Plan:
         arr[6] = int(schedule["curves_per_wave"])
         arr[12] = 1 if schedule.get("fused_spread") else 0
         arr[13] = 1 if schedule.get("persistent") else 0
-        _check(lib().fchi2_plan_set_schedule(self._h, arr, 14))
+        arr[14] = int(schedule.get("solve_sub_wave", 0))
+        _check(lib().fchi2_plan_set_schedule(self._h, arr, 15))
         return self.info()
 
     def profile(self, enable: bool = True):

@@ -143,3 +143,36 @@ def test_set_schedule_reproduces_the_tuned_plan():
     assert b.info() == info
     a.close()
     b.close()
+
+
+def test_solve_sub_wave_identical():
+    """The last FFT pass and the solve run on sub-waves (each sub-wave's solve
+    right after its spectra are written): the same kernels per curve, so rows,
+    chi2_0, flags, coefficients and the adjoint are identical bit for bit to
+    the whole-wave schedule."""
+    import torch
+    from tests.test_gpu_fused import same_bits
+    cur = synth.make("batch", n_curves=29, n_freq=2 ** 14, f_max=6.0, n_lo=20, n_hi=3000,
+                     span_hi=150.0)
+    t, x, s = to_dev(cur)
+    outs = []
+    for wave, sub in ((10, 0), (10, 3), (29, 7), (29, 0)):
+        note(f"sub-wave: wave {wave}, last pass and solve on {sub or wave}")
+        plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed",
+                      keep_for_backward=True)
+        info = plan.set_schedule(dict(plan.info(), curves_per_wave=wave, solve_sub_wave=sub))
+        assert info["curves_per_wave"] == wave and info["solve_sub_wave"] == sub
+        d, c0, fl, coef = plan.search_coeffs(t, x, s)
+        d2, _, _ = plan.search(t, x, s)
+        g = torch.zeros_like(d2)
+        g[:, cur.H - 1, 100:110] = 1.0
+        gx, gs = plan.backward(t, x, s, g)
+        torch.cuda.synchronize()
+        outs.append([v.cpu() for v in (d, c0, fl, coef, d2, gx, gs)])
+        plan.close()
+    for o in outs[1:]:
+        for u, v in zip(outs[0], o):
+            assert same_bits(u, v)
+    with pytest.raises(F.FChi2Error):
+        plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed")
+        plan.set_schedule(dict(plan.info(), curves_per_wave=4, solve_sub_wave=5))
