@@ -159,9 +159,10 @@ def stage_source_hash(stage):
 
 
 def measured_traffic(name):
-    """HBM bytes per launch of each stage from a committed rocprofv3 PMC
-    summary (profiles/<name>_hbm_traffic.md), or {} if there is none, or None
-    for a stage whose kernel source changed since the counters were taken."""
+    """HBM bytes per curve of each stage's launch from a committed rocprofv3
+    PMC summary (profiles/<name>_hbm_traffic.md: bytes per launch of
+    curves_per_launch curves), or {} if there is none, or None for a stage
+    whose kernel source changed since the counters were taken."""
     import re
     path = os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.md")
     if not os.path.exists(path):
@@ -171,10 +172,11 @@ def measured_traffic(name):
         return {}
     meta = json.loads(m.group(1))
     out = {}
+    per = max(1, int(meta.get("curves_per_launch", 1)))
     for st, nbytes in meta.get("bytes_per_launch", {}).items():
         hx = stage_source_hash(st)
         ok = hx is not None and hx == meta.get("source_sha256_16", {}).get(st)
-        out[st] = int(nbytes) if ok else None
+        out[st] = (float(nbytes) / per) if ok else None
     return out
 
 
@@ -209,7 +211,7 @@ def oracle_pool(tasks):
     return res, time.perf_counter() - t0, cores
 
 
-BINS_EACH = 30  # oracle bins on every curve of the batch sample
+BINS_EACH = 80  # oracle bins on every curve of the batch sample
 
 
 def batch_sample(cur, seed=7, n_strat=32, bins_strat=96, bins_each=BINS_EACH):
@@ -312,7 +314,8 @@ def workload_line(name, steps, warmup, precision=None, parity_bins=256, seed=11,
                            want_flags=False)
     b, o = (4, 4) if prec == "mixed" else (8, 8)
     roof, sections, stage_ms = stage_roofline(cur, st, 2, b, o, schedule)
-    roof["traffic"] = measured_traffic(f"{name}_{prec}").get(roof["kernel"])
+    tr = measured_traffic(f"{name}_{prec}").get(roof["kernel"])
+    roof["traffic"] = None if tr is None else int(round(tr))  # one curve per launch
     units = cur.n_freq * cur.H
     # Parity on seeded bins (plus the caller's bins), oracle on all cores.
     rng = np.random.default_rng(seed)
@@ -627,8 +630,19 @@ def main(argv=None):
         log(f"batched (graph replay): {ms_step:.3f} ms/step over {a.steps} steps "
             f"(wall {wall_ms:.3f})")
         ref = dchi2.clone()
-        st = profiled_pass(plan, t, x, s, stream, dchi2=dchi2, chi2_0=chi2_0, workspace=ws,
+        # Stage split: a one-stream plan on the same schedule, so that each
+        # kernel's launches are timed undisturbed (in the timed schedule the
+        # next wave's spreading runs beside the current wave's passes).
+        plan1 = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision,
+                       one_stream=True)
+        plan1.set_schedule(schedule)
+        ws1 = plan1.workspace()
+        plan1.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, workspace=ws1, want_flags=False,
+                     stream=stream)
+        st = profiled_pass(plan1, t, x, s, stream, dchi2=dchi2, chi2_0=chi2_0, workspace=ws1,
                            want_flags=False)
+        plan1.close()
+        del ws1
         ms_plain, same = None, None
         if not a.no_plain:
             # Plain form: the same kernels and schedule, one curve per call, no graph.
@@ -653,7 +667,18 @@ def main(argv=None):
         ms_top = e0.elapsed_time(e1) / a.steps
         log(f"fused top-{K}: {ms_top:.3f} ms/step")
     roof, sections, stage_ms = stage_roofline(cur, st, 1, 4, 4, schedule)
-    roof["traffic"] = measured_traffic("batch_mixed").get(roof["kernel"])
+    tr = measured_traffic("batch_mixed").get(roof["kernel"])
+    waves = st["solve"][1] if st.get("solve", (0, 0))[1] else None  # one solve per wave
+    roof["traffic"] = None if (tr is None or not waves) else int(round(
+        tr * cur.n_curves / waves))
+    roof["stage_split"] = "one-stream plan on the timed schedule (kernels undisturbed)"
+    # The whole step on the timed search itself (its spreading overlaps the
+    # passes, so the stages' sum exceeds it).
+    ws_gb = sections["whole_step"]["gb_per_step_sec8d"]
+    sections["whole_step"].update({
+        "ms": round(ms_step, 4), "gbs": round(ws_gb / (ms_step * 1e-3), 1),
+        "frac": round(ws_gb / (ms_step * 1e-3) / HBM_PEAK_GBS, 4),
+        "stage_sum_ms": round(sum(stage_ms.values()), 4)})
     out = {
         "metric": METRIC, "value": round(units / (ms_step * 1e-3), 1), "unit": "freq*H/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
@@ -698,12 +723,12 @@ def main(argv=None):
             gates.append((fr >= 1.0 / span) & (kappa <= 1e2) if span > 0 else kappa <= 1e2)
         nb = sum(len(p) for _, p in order)
         v_cpu = nb * cur.H / el
-        # one core: a short in-process run on a stratified curve
-        c1 = strat[0]
-        b1 = sample[c1][:24]
+        # one core: every 32nd task of the same list, in this process
+        sub = tasks[::32]
         t1 = time.perf_counter()
-        _oracle_task((*cur.curve(c1), b1 * df, cur.H))
-        one = len(b1) * cur.H / (time.perf_counter() - t1)
+        for tk in sub:
+            _oracle_task(tk)
+        one = sum(len(tk[3]) for tk in sub) * cur.H / (time.perf_counter() - t1)
         out["cpu_baseline"] = {
             "value": round(v_cpu, 2), "unit": "freq*H/s", "cores": cores, "kind": "oracle",
             "sample": (f"{nb} bins (all H'=1..{cur.H}) of the batch workload: {len(strat)} "

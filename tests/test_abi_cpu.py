@@ -65,7 +65,7 @@ def _plan(**kw):
     (dict(H=9, flags=F.KEEP_FOR_BACKWARD), F.ERR_UNSUPPORTED, "backward needs H <= 8"),
     (dict(H=3, flags=F.KEEP_FOR_BACKWARD | F.WIDE_SOLVE), F.ERR_UNSUPPORTED, "backward needs"),
     (dict(H=12, first_bin=4096), F.ERR_UNSUPPORTED, "band plans need H <= 8"),
-    (dict(flags=32), F.ERR_ARG, "flag"),
+    (dict(flags=64), F.ERR_ARG, "flag"),
 ])
 def test_plan_argument_errors(kw, code, frag):
     st, msg = _plan(**kw)

@@ -25,10 +25,11 @@ def test_overlap_identical_outputs_and_adjoint():
     cur = _cur()
     t, x, s = to_dev(cur)
     outs = []
-    for wave, sub in ((43, 0), (10, 0), (21, 5), (7, 0)):
-        note(f"overlap: wave {wave}, sub {sub}")
+    for wave, sub, one in ((43, 0, False), (10, 0, False), (21, 5, False), (7, 0, False),
+                           (10, 0, True)):
+        note(f"overlap: wave {wave}, sub {sub}, one stream {one}")
         plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed",
-                      keep_for_backward=True)
+                      keep_for_backward=True, one_stream=one)
         plan.set_schedule(dict(plan.info(), curves_per_wave=wave, solve_sub_wave=sub))
         d, c0, fl, coef = plan.search_coeffs(t, x, s)
         d2, _, fl2 = plan.search(t, x, s)
