@@ -564,17 +564,19 @@ bool use_overlap(const fchi2_plan_s* pl, int n) {
 }
 
 // The forward chain with the spreading of wave i + 1 on the side stream while
-// the main stream runs wave i's FFT passes and solve.  Wave i spreads into
-// grid A buffer i % 2 (halves of the grid A region) with table i % 2 (halves
-// of the table region); the side stream waits for the first pass that last
-// read that buffer (wave i - 2), the main stream for wave i's spreading.
-// Every kernel is the staged search's on the same curves, so the results are
-// identical bit for bit.  Every piece of side-stream work is waited on by the
-// main stream before the call returns to it, so graph capture joins.
-fchi2_status_t enqueue_search_overlap(fchi2_plan_s* pl, int cbeg, int cend, const double* t,
-                                      const double* x, const double* sigma, char* ws,
-                                      void* dchi2, uint8_t* flags, hipStream_t st,
-                                      void* coef) {
+// the main stream runs wave i's FFT passes and what follows them (`tail`,
+// made per wave from (c0, nw, spectra): the solve, or the solve with the
+// candidate selection).  Wave i spreads into grid A buffer i % 2 (halves of
+// the grid A region) with table i % 2 (halves of the table region); the side
+// stream waits for the first pass that last read that buffer (wave i - 2),
+// the main stream for wave i's spreading.  Every kernel is the one-stream
+// search's on the same curves, so the results are identical bit for bit.
+// Every piece of side-stream work is waited on by the main stream before the
+// call returns to it, so graph capture joins.
+using WaveTail = std::function<AfterLast(int, int, void*)>;
+fchi2_status_t enqueue_waves_overlap(fchi2_plan_s* pl, int cbeg, int cend, const double* t,
+                                     const double* x, const double* sigma, char* ws,
+                                     hipStream_t st, int sub, const WaveTail& tail) {
   Moments* mom = (Moments*)(ws + pl->off_mom);
   const bool keep = pl->desc.flags & FCHI2_KEEP_FOR_BACKWARD;
   const size_t zc_curve = (size_t)pl->g.P * 2 * pl->g.n_freq * pl->elem;
@@ -605,21 +607,13 @@ fchi2_status_t enqueue_search_overlap(fchi2_plan_s* pl, int cbeg, int cend, cons
       return hip_fail(e, "hipEventRecord");
     if ((e = hipStreamWaitEvent(st, pl->ev_spread[b], 0)) != hipSuccess)
       return hip_fail(e, "hipStreamWaitEvent");
-    const AfterLast solve = [&](int off, int n) -> fchi2_status_t {
-      PROF_BEGIN(FCHI2_PROF_SOLVE);
-      hipError_t es = launch_solve(pl->fp64, (char*)zc + (size_t)off * zc_curve, pl->d_D, mom,
-                                   pl->g, c0 + off, n, pl->eps_piv, dchi2, flags, st, coef,
-                                   (pl->desc.flags & FCHI2_WIDE_SOLVE) != 0);
-      if (es != hipSuccess) return hip_fail(es, "solve");
-      PROF_END();
-      return FCHI2_OK;
-    };
+    const AfterLast after = tail(c0, nw, zc);
     const AfterFirst first_done = [&]() -> fchi2_status_t {
       hipError_t ef = hipEventRecord(pl->ev_first[b], st);
       return ef == hipSuccess ? FCHI2_OK : hip_fail(ef, "hipEventRecord");
     };
     fchi2_status_t s = enqueue_fft(pl, MODE_FWD, gA, gB, zc, mom, c0, nw, st, nullptr, nullptr,
-                                   nullptr, pl->solve_sub, &solve, &first_done);
+                                   nullptr, sub, &after, &first_done);
     if (s != FCHI2_OK) return s;
   }
   return FCHI2_OK;
@@ -639,8 +633,21 @@ fchi2_status_t enqueue_search(fchi2_plan_s* pl, int cbeg, int cend, const double
   PROF_END();
   if (use_persist(pl) && !coef)
     return enqueue_persistent(pl, cbeg, cend, t, x, sigma, ws, dchi2, flags, st);
-  if (use_overlap(pl, cend - cbeg))
-    return enqueue_search_overlap(pl, cbeg, cend, t, x, sigma, ws, dchi2, flags, st, coef);
+  if (use_overlap(pl, cend - cbeg)) {
+    const size_t zc_curve = (size_t)pl->g.P * 2 * pl->g.n_freq * pl->elem;
+    const WaveTail tail = [=](int c0, int, void* zc) -> AfterLast {
+      return [=](int off, int n) -> fchi2_status_t {
+        PROF_BEGIN(FCHI2_PROF_SOLVE);
+        hipError_t es = launch_solve(pl->fp64, (char*)zc + (size_t)off * zc_curve, pl->d_D, mom,
+                                     pl->g, c0 + off, n, pl->eps_piv, dchi2, flags, st, coef,
+                                     (pl->desc.flags & FCHI2_WIDE_SOLVE) != 0);
+        if (es != hipSuccess) return hip_fail(es, "solve");
+        PROF_END();
+        return FCHI2_OK;
+      };
+    };
+    return enqueue_waves_overlap(pl, cbeg, cend, t, x, sigma, ws, st, pl->solve_sub, tail);
+  }
   const bool keep = pl->desc.flags & FCHI2_KEEP_FOR_BACKWARD;
   const size_t zc_curve = (size_t)pl->g.P * 2 * pl->g.n_freq * pl->elem;
   for (int c0 = cbeg; c0 < cend; c0 += pl->wave) {
@@ -695,6 +702,23 @@ fchi2_status_t enqueue_search_top(fchi2_plan_s* pl, const double* t, const doubl
   const size_t zc_curve = (size_t)pl->g.P * 2 * pl->g.n_freq * pl->elem;
   const TopScratch sc = top_scratch_carve(ws + top_ws_offset(pl), pl->g.n_freq, pl->g.H,
                                           pl->wave_max, K);
+  if (use_overlap(pl, nc)) {
+    const WaveTail tail = [=](int c0, int nw, void* zc) -> AfterLast {
+      return [=](int, int) -> fchi2_status_t {
+        PROF_BEGIN(FCHI2_PROF_SOLVE);
+        hipError_t es = launch_solve_top(pl->fp64, zc, pl->d_D, mom, pl->g, c0, nw, pl->eps_piv,
+                                         hrow, k_lo, K, sc, st);
+        if (es != hipSuccess) return hip_fail(es, "solve with candidate selection");
+        PROF_END();
+        PROF_BEGIN(FCHI2_PROF_TOP_MERGE);
+        es = launch_top_merge(mom, pl->g, c0, nw, hrow, K, sc, out, st);
+        if (es != hipSuccess) return hip_fail(es, "candidate merge");
+        PROF_END();
+        return FCHI2_OK;
+      };
+    };
+    return enqueue_waves_overlap(pl, 0, nc, t, x, sigma, ws, st, 0, tail);
+  }
   for (int c0 = 0; c0 < nc; c0 += pl->wave) {
     const int nw = (nc - c0) < pl->wave ? (nc - c0) : pl->wave;
     void* gA = ws + pl->off_gA;

@@ -86,3 +86,24 @@ def test_overlap_subset_graph_and_profile():
     waves = (cur.n_curves + 5) // 6
     assert pr["spread"][1] == waves and pr["fft_first"][1] == waves and pr["solve"][1] == waves
     plan.close()
+
+
+def test_overlap_top_candidates_identical():
+    """The search with the significance epilogue on overlapped waves selects
+    the same candidates with the same values as on one wave."""
+    import torch
+    cur = _cur()
+    t, x, s = to_dev(cur)
+    outs = []
+    for wave in (43, 10, 7):
+        note(f"overlap: top-16 search, wave {wave}")
+        plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed")
+        plan.set_schedule(dict(plan.info(), curves_per_wave=wave))
+        top = plan.search_top(t, x, s, K=16, k_lo=3)
+        torch.cuda.synchronize()
+        outs.append({k: v.cpu() for k, v in top.items()})
+        plan.close()
+    for o in outs[1:]:
+        for k in outs[0]:
+            assert same_bits(outs[0][k], o[k]), k
+    assert (outs[0]["idx"] >= 0).any()
