@@ -518,8 +518,8 @@ fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* 
 
 /*
  * Autotuner.  Times every candidate schedule of the plan on the caller's data
- * (the FFT digit splits with the fewest passes and the most balanced splits
- * with one pass more, for FP32 grids each on FFT tiles of 4096 or 8192
+ * (the FFT digit splits with the fewest passes and, for grids of at most
+ * 2^20 cells, the most balanced splits with one pass more, for FP32 grids each on FFT tiles of 4096 or 8192
  * elements per pass, spreading tiles of 1024 to 8192 cells or, outside band
  * plans, the spreading fused into the first FFT pass, waves of wave_max,
  * wave_max/2, /4, /6, /8, /10, /12 curves with the last FFT pass and the

@@ -184,7 +184,8 @@ bool plan_fft(int logL, int LE, FftPlan& fp) {
 }
 
 // Valid digit splits of L = 2^logL for the autotuner: every split with the
-// smallest pass count, plus the most balanced splits with one pass more.  The
+// smallest pass count, plus (L <= 2^20) the most balanced splits with one
+// pass more.  The
 // extra pass costs a full read and write of the grids, but larger tiles in T
 // (columns per tile) give longer contiguous runs: at L = 2^18 the two-pass
 // split 2^9 x 2^9 moves runs of 8 elements (64 B), three passes of 2^6 move
@@ -207,7 +208,13 @@ std::vector<FftPlan> fft_splits_uniform(int logL, int LE) {
     }
     return ok;
   };
-  for (int np = best.np; np <= best.np + 1 && np <= kMaxPasses; ++np) {
+  // The extra pass pays only on short grids (at L = 2^18 three passes of 2^6
+  // beat two of 2^9); on grids above 2^20 cells it is slower and each pass
+  // adds a rounding of the stored grid: measured on the stress workload
+  // (L = 2^26, mixed), every four-pass split gave 6.3e-6 to 1.4e-5 against
+  // the oracle where the three-pass splits gave 6.0e-6 to 9.9e-6.
+  const int np_max = logL > 20 ? best.np : best.np + 1;
+  for (int np = best.np; np <= np_max && np <= kMaxPasses; ++np) {
     std::vector<FftPlan> found;
     int total = 1;
     for (int q = 0; q < np; ++q) total *= (hi - lo + 1);
