@@ -608,7 +608,7 @@ def main(argv=None):
     x = torch.from_numpy(cur.x).cuda()
     s = torch.from_numpy(cur.sigma).cuda()
     plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision,
-                  graph=True)
+                  graph=True, two_streams=True)
     ws = plan.workspace()
     t0 = time.perf_counter()
     if sched_arg is not None:
@@ -633,8 +633,7 @@ def main(argv=None):
         # Stage split: a one-stream plan on the same schedule, so that each
         # kernel's launches are timed undisturbed (in the timed schedule the
         # next wave's spreading runs beside the current wave's passes).
-        plan1 = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision,
-                       one_stream=True)
+        plan1 = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision)
         plan1.set_schedule(schedule)
         ws1 = plan1.workspace()
         plan1.search(t, x, s, dchi2=dchi2, chi2_0=chi2_0, workspace=ws1, want_flags=False,

@@ -80,11 +80,16 @@ typedef enum {
                                       results are the same bit for bit; the
                                       autotuner may change it; not for band
                                       plans                                  */
-#define FCHI2_ONE_STREAM 32u       /* never use a second stream: no
-                                      overlapped wave schedule (the same
-                                      results; for callers that need all
-                                      work on their stream, and for
-                                      measuring each kernel undisturbed)   */
+#define FCHI2_TWO_STREAMS 32u      /* allow the overlapped wave schedule:
+                                      the plan creates a second stream
+                                      (default priority) on which the next
+                                      wave's spreading runs beside the
+                                      current wave's passes, joined back
+                                      into the caller's stream by events
+                                      (stream order and graph capture are
+                                      kept; the same results bit for bit).
+                                      Without it all work is on the
+                                      caller's stream                     */
 #define FCHI2_PERSISTENT 16u       /* search all curves in one persistent
                                       launch: workgroups claim curves from a
                                       device work queue and run each curve's
@@ -133,7 +138,7 @@ typedef struct {
   int32_t precision;         /* fchi2_precision_t                             */
   uint32_t flags;            /* FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH |
                                 FCHI2_FUSED_SPREAD | FCHI2_WIDE_SOLVE |
-                                FCHI2_PERSISTENT | FCHI2_ONE_STREAM           */
+                                FCHI2_PERSISTENT | FCHI2_TWO_STREAMS          */
   int32_t kernel_width;      /* spreading kernel taps, 0 = default
                                 (14 for FP64, 10 for MIXED); 4..16; or 1 =
                                 floor gridding as printed in Section 3b (each
@@ -188,9 +193,9 @@ int64_t fchi2_auto_n_freq(int32_t H, double f_max, double oversampling, double s
  * zero-padded arrays), the FFT pass split and the spreading kernel, and
  * builds its device tables (twiddles, deconvolution) on `stream`, waiting for
  * them.  Allocates device memory for those tables (owned by the plan); a
- * plan of several curves (not a band plan, no FCHI2_ONE_STREAM) also creates
- * a second stream of default priority and a few events (owned by the plan)
- * for the overlapped wave schedule of fchi2_search.  On success *out receives the plan.
+ * plan of several curves with FCHI2_TWO_STREAMS (not a band plan) also
+ * creates a second stream of default priority and a few events (owned by the
+ * plan) for the overlapped wave schedule of fchi2_search.  On success *out receives the plan.
  * The grids are periodic: when 2H * span * f_max / n_freq exceeds 1 the
  * harmonic phases wrap around them, which is handled (the transforms at
  * integer bins are unchanged by whole periods); the tile tables cover enough
@@ -222,12 +227,12 @@ int64_t fchi2_total_points(fchi2_plan_t plan);
  *  chi2_0       device FP64 [n_curves] or NULL
  *  flags        device uint8 [n_curves][n_freq] (FCHI2_BIN_* / FCHI2_CURVE_*)
  *               or NULL
- * With waves of at most half the buffers' capacity (a tuned or set
- * schedule), the spreading of the next wave runs on the plan's second stream
- * while `stream` runs the current wave's FFT passes and solve; the two are
- * ordered by events and all of it is joined back into `stream` (stream
- * order and graph capture behave as for one stream).  The results are the
- * same bit for bit.
+ * All work is enqueued on `stream`, except with FCHI2_TWO_STREAMS and waves
+ * of at most half the buffers' capacity (a tuned or set schedule): then the
+ * spreading of the next wave runs on the plan's second stream while `stream`
+ * runs the current wave's FFT passes and solve; the two are ordered by
+ * events and all of it is joined back into `stream` (stream order and graph
+ * capture behave as for one stream).  The results are the same bit for bit.
  * Errors: FCHI2_ERR_ARG (NULL plan/pointer, misaligned or small workspace),
  * FCHI2_ERR_HIP.
  */

@@ -870,7 +870,7 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   if (d.precision != FCHI2_FP64 && d.precision != FCHI2_MIXED)
     return fail(FCHI2_ERR_ARG, "precision must be FCHI2_FP64 or FCHI2_MIXED");
   if (d.flags & ~(uint32_t)(FCHI2_KEEP_FOR_BACKWARD | FCHI2_GRAPH | FCHI2_FUSED_SPREAD |
-                            FCHI2_WIDE_SOLVE | FCHI2_PERSISTENT | FCHI2_ONE_STREAM))
+                            FCHI2_WIDE_SOLVE | FCHI2_PERSISTENT | FCHI2_TWO_STREAMS))
     return fail(FCHI2_ERR_ARG, "unknown flag bits 0x%x", d.flags);
   if ((d.H > kHMax || (d.flags & FCHI2_WIDE_SOLVE)) && (d.flags & FCHI2_KEEP_FOR_BACKWARD))
     return fail(FCHI2_ERR_UNSUPPORTED, "backward needs H <= %d (the register solver)", kHMax);
@@ -1104,7 +1104,7 @@ fchi2_status_t fchi2_plan(const fchi2_plan_desc_t* desc, void* stream, fchi2_pla
   if ((e = scratch_address(&sp)) != hipSuccess)
     return cleanup_fail(hip_fail(e, "hipGetSymbolAddress(scratch)"));
   // The spreading stream of the overlapped wave schedule (default priority).
-  if (d.n_curves > 1 && !g.band && !(d.flags & FCHI2_ONE_STREAM)) {
+  if (d.n_curves > 1 && !g.band && (d.flags & FCHI2_TWO_STREAMS)) {
     if ((e = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking)) != hipSuccess)
       return cleanup_fail(hip_fail(e, "hipStreamCreateWithFlags"));
     for (hipEvent_t* ev : {&pl->ev_start, &pl->ev_spread[0], &pl->ev_spread[1], &pl->ev_first[0],

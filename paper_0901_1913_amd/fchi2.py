@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfchi2.so")
 
 OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = range(6)
 FP64, MIXED = 0, 1
-KEEP_FOR_BACKWARD, GRAPH, FUSED_SPREAD, WIDE_SOLVE, PERSISTENT, ONE_STREAM = 1, 2, 4, 8, 16, 32
+KEEP_FOR_BACKWARD, GRAPH, FUSED_SPREAD, WIDE_SOLVE, PERSISTENT, TWO_STREAMS = 1, 2, 4, 8, 16, 32
 NOALLOC_SCRATCH_BYTES = 64 << 20
 H_MAX = 16
 H_MAX_REGISTER = 8
@@ -215,7 +215,7 @@ class Plan:
                  graph: bool = False, kernel_width: int = 0, curves_per_wave: int = 0,
                  first_bin: int = 0, oversampling: float = 0.0, t_span=None,
                  fused_spread: bool = False, wide_solve: bool = False,
-                 persistent: bool = False, one_stream: bool = False, stream=None):
+                 persistent: bool = False, two_streams: bool = False, stream=None):
         torch = _torch()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         if off.ndim != 1 or off.shape[0] < 2:
@@ -225,7 +225,7 @@ class Plan:
         self._off = off
         flags = ((KEEP_FOR_BACKWARD if keep_for_backward else 0) | (GRAPH if graph else 0)
                  | (FUSED_SPREAD if fused_spread else 0) | (WIDE_SOLVE if wide_solve else 0)
-                 | (PERSISTENT if persistent else 0) | (ONE_STREAM if one_stream else 0))
+                 | (PERSISTENT if persistent else 0) | (TWO_STREAMS if two_streams else 0))
         desc = PlanDesc(
             n_curves=off.shape[0] - 1,
             offsets=off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),

@@ -1,9 +1,10 @@
-"""The overlapped wave schedule (waves of at most half the buffers' capacity:
-the next wave's spreading on a second stream while the current wave's FFT
-passes and solve run) launches the staged search's kernels on the same
-curves, so every output is identical bit for bit to the one-stream schedule:
-rows, chi2_0, flags, coefficients, the adjoint, curve subsets, graph replays
-(captured across both streams) and profiled runs."""
+"""The overlapped wave schedule (FCHI2_TWO_STREAMS, waves of at most half the
+buffers' capacity: the next wave's spreading on a second stream while the
+current wave's FFT passes and solve run) launches the staged search's
+kernels on the same curves, so every output is identical bit for bit to the
+one-stream schedule: rows, chi2_0, flags, coefficients, the adjoint, curve
+subsets, graph replays (captured across both streams), profiled runs and the
+top-K epilogue."""
 import numpy as np
 import pytest
 
@@ -25,11 +26,11 @@ def test_overlap_identical_outputs_and_adjoint():
     cur = _cur()
     t, x, s = to_dev(cur)
     outs = []
-    for wave, sub, one in ((43, 0, False), (10, 0, False), (21, 5, False), (7, 0, False),
-                           (10, 0, True)):
-        note(f"overlap: wave {wave}, sub {sub}, one stream {one}")
+    for wave, sub, two in ((43, 0, True), (10, 0, True), (21, 5, True), (7, 0, True),
+                           (10, 0, False)):
+        note(f"overlap: wave {wave}, sub {sub}, two streams {two}")
         plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed",
-                      keep_for_backward=True, one_stream=one)
+                      keep_for_backward=True, two_streams=two)
         plan.set_schedule(dict(plan.info(), curves_per_wave=wave, solve_sub_wave=sub))
         d, c0, fl, coef = plan.search_coeffs(t, x, s)
         d2, _, fl2 = plan.search(t, x, s)
@@ -56,7 +57,8 @@ def test_overlap_subset_graph_and_profile():
     rd, rc, rf = rd.cpu(), rc.cpu(), rf.cpu()
     ref.close()
     note("overlap: curve subset")
-    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed", graph=True)
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed", graph=True,
+                  two_streams=True)
     plan.set_schedule(dict(plan.info(), curves_per_wave=6))
     d = torch.full((cur.n_curves, cur.H, cur.n_freq), -1.0, dtype=torch.float32, device="cuda")
     c0 = torch.full((cur.n_curves,), -1.0, dtype=torch.float64, device="cuda")
@@ -97,7 +99,8 @@ def test_overlap_top_candidates_identical():
     outs = []
     for wave in (43, 10, 7):
         note(f"overlap: top-16 search, wave {wave}")
-        plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed")
+        plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed",
+                      two_streams=True)
         plan.set_schedule(dict(plan.info(), curves_per_wave=wave))
         top = plan.search_top(t, x, s, K=16, k_lo=3)
         torch.cuda.synchronize()
