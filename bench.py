@@ -247,23 +247,29 @@ def parity_summary(errs, gates):
             "max_rel_err_all": float(a.max())}
 
 
+_LAST_MEDIAN = {}
+
+
 def time_search(plan, t, x, s, steps, warmup, stream, **kw):
-    """Median-free mean over `steps` searches after `warmup`, HIP events on
-    the search stream, no per-launch events inside the timed region."""
+    """Mean over `steps` searches after `warmup` (HIP events on the search
+    stream, one between consecutive searches, none inside a search); the
+    median of the per-search times is kept in _LAST_MEDIAN["ms"]."""
     import torch
     d = kw.pop("dchi2")
     for _ in range(warmup):
         plan.search(t, x, s, dchi2=d, stream=stream, **kw)
     stream.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     w0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
+    ev[0].record(stream)
+    for i in range(steps):
         plan.search(t, x, s, dchi2=d, stream=stream, **kw)
-    e1.record(stream)
+        ev[i + 1].record(stream)
     stream.synchronize()
     wall = time.perf_counter() - w0
-    return e0.elapsed_time(e1) / steps, 1e3 * wall / steps
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    _LAST_MEDIAN["ms"] = float(np.median(per))
+    return ev[0].elapsed_time(ev[steps]) / steps, 1e3 * wall / steps
 
 
 def profiled_pass(plan, t, x, s, stream, reps=1, **kw):
@@ -279,12 +285,26 @@ def profiled_pass(plan, t, x, s, stream, reps=1, **kw):
 
 
 _ORACLE_CACHE = {}
+_BINS_CACHE = {}
 
 
-def workload_line(name, steps, warmup, precision=None, parity_bins=256, seed=11,
-                  extra_bins=None, schedule=None, tune_cache=None):
+def peak_and_low_bins(row, k_lo, n_peaks=32, halo=2, n_low=32):
+    """The n_peaks highest strict local maxima of a Delta chi2 row (bins >= k_lo)
+    +- halo and the n_low lowest bins from k_lo up: where the oracle is also
+    evaluated (it computes its own values there)."""
+    k = np.arange(max(k_lo, 1), row.shape[0] - 1)
+    is_max = (row[k] > row[k - 1]) & (row[k] >= row[k + 1])
+    pk = k[is_max][np.argsort(-row[k[is_max]], kind="stable")[:n_peaks]]
+    around = (pk[:, None] + np.arange(-halo, halo + 1)[None, :]).ravel()
+    return np.concatenate([around, np.arange(k_lo, k_lo + n_low)])
+
+
+def workload_line(name, steps, warmup, precision=None, parity_bins=2048, seed=11,
+                  extra_bins=None, schedule=None, tune_cache=None, full_grid=False):
     """Timing (autotuned, or on the given schedule), stage split, roofline and
-    oracle parity on sampled bins of one single-curve workload."""
+    oracle parity of one single-curve workload: on every bin (full_grid), or
+    on parity_bins seeded bins, the 32 highest local maxima of the H row +-2,
+    the 32 lowest bins from f = 1/span up and the caller's extra bins."""
     import torch
     from paper_0901_1913_amd import fchi2 as F
     from paper_0901_1913_amd import synth
@@ -316,13 +336,25 @@ def workload_line(name, steps, warmup, precision=None, parity_bins=256, seed=11,
     roof, sections, stage_ms = stage_roofline(cur, st, 2, b, o, schedule)
     tr = measured_traffic(f"{name}_{prec}").get(roof["kernel"])
     roof["traffic"] = None if tr is None else int(round(tr))  # one curve per launch
+    ms_median = _LAST_MEDIAN["ms"]
     units = cur.n_freq * cur.H
-    # Parity on seeded bins (plus the caller's bins), oracle on all cores.
-    rng = np.random.default_rng(seed)
-    bins = rng.choice(np.arange(1, cur.n_freq), size=parity_bins, replace=False)
-    if extra_bins is not None:
-        bins = np.concatenate([bins, extra_bins])
+    # Parity bins (oracle on the host's CPU share).
+    span = float(cur.t[-1] - cur.t[0])
+    k_lo = int(np.ceil(cur.n_freq / (span * cur.f_max)))
+    bkey = (name, full_grid, parity_bins, seed)
+    if full_grid:
+        bins = np.arange(1, cur.n_freq)
+    elif bkey in _BINS_CACHE:  # the FP64 line of a workload reuses the mixed line's bins
+        bins = _BINS_CACHE[bkey]
+    else:
+        rng = np.random.default_rng(seed)
+        bins = rng.choice(np.arange(1, cur.n_freq), size=parity_bins, replace=False)
+        row = d[0, cur.H - 1].double().cpu().numpy()
+        bins = np.concatenate([bins, peak_and_low_bins(row, k_lo)])
+        if extra_bins is not None:
+            bins = np.concatenate([bins, extra_bins])
     bins = np.unique(bins[(bins >= 1) & (bins < cur.n_freq)])
+    _BINS_CACHE[bkey] = bins
     dd = d.double().cpu().numpy()[0][:, bins]
     plan.close()
     key = (name, bins.tobytes())
@@ -341,15 +373,24 @@ def workload_line(name, steps, warmup, precision=None, parity_bins=256, seed=11,
     fr = bins * (cur.f_max / cur.n_freq)
     gate = (fr >= 1.0 / span) & (kappa <= kmax)
     par = parity_summary([err], [gate])
-    par.update({"bins": int(len(bins)), "gate": f"k >= 1, f >= 1/span, kappa <= {kmax:g}"})
-    log(f"{name} {prec}: {ms:.4f} ms/search, parity max {par['max_rel_err_gated']:.3e}")
+    par.update({"bins": int(len(bins)), "gate": f"k >= 1, f >= 1/span, kappa <= {kmax:g}",
+                "sample": ("every bin" if full_grid else
+                           f"{parity_bins} seeded bins, the 32 highest local maxima of the "
+                           f"H row +-2, the 32 lowest bins from 1/span"
+                           + (", extra bins" if extra_bins is not None else ""))})
+    log(f"{name} {prec}: {ms:.4f} ms/search, parity max {par['max_rel_err_gated']:.3e} "
+        f"on {len(bins)} bins")
     return {"workload": name, "n": int(cur.t.shape[0]), "H": cur.H, "n_freq": cur.n_freq,
             "f_max": cur.f_max, "precision": prec, "ms_per_search": round(ms, 5),
+            "ms_median": round(ms_median, 5),
             "wall_ms_per_search": round(wall, 5), "value": round(units / (ms * 1e-3), 1),
             "unit": "freq*H/s", "schedule": schedule, "autotune_s": round(tune_s, 2),
             "stages_ms": stage_ms, "roofline": roof, "sections": sections, "parity": par,
             "oracle": {"value": round(len(bins) * cur.H / el, 2), "cores": cores,
-                       "bins": int(len(bins)), "wall_s": round(el, 2)}}
+                       "bins": int(len(bins)), "wall_s": round(el, 2),
+                       "full_grid_s": (round(el, 2) if full_grid else
+                                       round(units / (len(bins) * cur.H / el), 1)),
+                       "full_grid_s_kind": "measured" if full_grid else "extrapolated"}}
 
 
 def multi_vs_curves(steps):
@@ -409,10 +450,15 @@ def multi_vs_curves(steps):
 def gradient_timing(steps):
     """Adjoint of the search on the diff workload: forward with the spectra
     kept, top-16 strict local maxima of the H row frozen, then the gradient
-    of the sum of their Delta chi2 with respect to x and sigma."""
+    of the sum of their Delta chi2 with respect to x and sigma.  Forward and
+    backward timed without per-launch events (the backward's stage split
+    from a separate profiled pass); forward parity on 512 seeded bins, the
+    32 highest local maxima +-2 and the 32 lowest bins; the gradient against
+    the oracle's closed form (relative l2 and element-wise)."""
     import torch
     from paper_0901_1913_amd import fchi2 as F
     from paper_0901_1913_amd import synth
+    from oracle import fchi2_oracle as ora
     cur = synth.make("diff")
     plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision,
                   keep_for_backward=True)
@@ -423,10 +469,11 @@ def gradient_timing(steps):
     d, _, _ = plan.search(t, x, s)
     span = float(cur.t[-1] - cur.t[0])
     df = cur.f_max / cur.n_freq
-    idx = plan.top_peaks(d, cur.H - 1, int(np.ceil(1.0 / (span * df))), 16)
+    k_lo = int(np.ceil(1.0 / (span * df)))
+    idx = plan.top_peaks(d, cur.H - 1, k_lo, 16)
     g = torch.zeros_like(d)
     g[0, cur.H - 1, idx[0]] = 1.0
-    plan.backward(t, x, s, g)
+    gx, gs = plan.backward(t, x, s, g)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -437,25 +484,51 @@ def gradient_timing(steps):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_f = e0.elapsed_time(e1) / steps
-    plan.profile(True)
     e0.record(stream)
     for _ in range(steps):
         gx, gs = plan.backward(t, x, s, g)
     e1.record(stream)
     torch.cuda.synchronize()
     ms_b = e0.elapsed_time(e1) / steps
+    plan.profile(True)
+    plan.backward(t, x, s, g)
     st = plan.profile_read()
     plan.profile(False)
+    # Parity: forward on the sample, gradient against the closed form.
+    row = d[0, cur.H - 1].double().cpu().numpy()
+    dd = d[0].double().cpu().numpy()
+    rng = np.random.default_rng(13)
+    bins = np.unique(np.concatenate([rng.choice(np.arange(1, cur.n_freq), 512, replace=False),
+                                     peak_and_low_bins(row, k_lo)]))
+    bins = bins[(bins >= 1) & (bins < cur.n_freq)]
+    chunks = np.array_split(bins, 4 * pool_size())
+    res, el, cores = oracle_pool([(cur.t, cur.x, cur.sigma, c * df, cur.H) for c in chunks
+                                  if len(c)])
+    d_ora = np.concatenate([r[0] for r in res], axis=1)
+    kappa = np.concatenate([r[1] for r in res])
+    err = ora.rel_err(dd[:, bins], d_ora)
+    gate = (bins * df >= 1.0 / span) & (kappa <= 1e2)
+    par = parity_summary([err], [gate])
+    pk = idx.cpu().numpy()[0]
+    rx, rs = ora.grad(cur.t, cur.x, cur.sigma, [(float(k) * df, cur.H, 1.0) for k in pk])
+    gxn, gsn = gx.cpu().numpy(), gs.cpu().numpy()
+    par.update({"bins": int(len(bins)), "gate": "k >= 1, f >= 1/span, kappa <= 100",
+                "grad_x_rel_l2": float(np.linalg.norm(gxn - rx) / np.linalg.norm(rx)),
+                "grad_sigma_rel_l2": float(np.linalg.norm(gsn - rs) / np.linalg.norm(rs)),
+                "grad_x_max_rel": float(np.abs(gxn - rx).max() / np.abs(rx).max()),
+                "grad_sigma_max_rel": float(np.abs(gsn - rs).max() / np.abs(rs).max())})
     plan.close()
     units = cur.n_freq * cur.H
-    log(f"gradient (diff): forward {ms_f:.4f} ms, backward {ms_b:.4f} ms")
+    log(f"gradient (diff): forward {ms_f:.4f} ms, backward {ms_b:.4f} ms, parity max "
+        f"{par['max_rel_err_gated']:.3e}, grad l2 {par['grad_x_rel_l2']:.2e}")
     return {"workload": "diff", "n": int(cur.t.shape[0]), "H": cur.H, "n_freq": cur.n_freq,
             "precision": cur.precision, "forward_ms": round(ms_f, 5),
             "backward_ms": round(ms_b, 5),
             "backward_value": round(units / (ms_b * 1e-3), 1), "unit": "freq*H/s",
-            "backward_stages_ms": {k: round(v[0] / steps, 5) for k, v in st.items()
+            "backward_stages_ms": {k: round(v[0], 5) for k, v in st.items()
                                    if v[1] and k.startswith("bwd")},
-            "schedule": schedule}
+            "schedule": schedule, "parity": par,
+            "oracle": {"cores": cores, "bins": int(len(bins)), "wall_s": round(el, 2)}}
 
 
 def variants_timing(steps):
@@ -627,8 +700,9 @@ def main(argv=None):
     with torch.cuda.stream(stream):
         ms_step, wall_ms = time_search(plan, t, x, s, a.steps, a.warmup, stream, dchi2=dchi2,
                                        chi2_0=chi2_0, workspace=ws, want_flags=False)
+        ms_median = _LAST_MEDIAN["ms"]
         log(f"batched (graph replay): {ms_step:.3f} ms/step over {a.steps} steps "
-            f"(wall {wall_ms:.3f})")
+            f"(median {ms_median:.3f}, wall {wall_ms:.3f})")
         ref = dchi2.clone()
         # Stage split: a one-stream plan on the same schedule, so that each
         # kernel's launches are timed undisturbed (in the timed schedule the
@@ -681,6 +755,7 @@ def main(argv=None):
     out = {
         "metric": METRIC, "value": round(units / (ms_step * 1e-3), 1), "unit": "freq*H/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
+        "ms_median": round(ms_median, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "batch", "n_curves": cur.n_curves, "n_total": n_tot,
@@ -745,17 +820,19 @@ def main(argv=None):
     torch.cuda.empty_cache()
     if not a.no_workloads:
         wl = {}
-        k0 = int(round(2 ** 14 / 10.0 / 2.37))
-        wl["plain_fp64"] = workload_line("plain", a.steps, a.warmup,
-                                         extra_bins=np.arange(k0 - 4, k0 + 5),
+        wl["plain_fp64"] = workload_line("plain", a.steps, a.warmup, full_grid=True,
                                          tune_cache=a.tune_cache)
-        wl["long_mixed"] = workload_line("long", a.steps, a.warmup, tune_cache=a.tune_cache)
+        # long: also +-8 bins around 1 and 2 cycles/day (the diurnal aliases)
+        nf_l, fm_l = 2 ** 22, 50.0
+        alias = np.concatenate([int(round(c * nf_l / fm_l)) + np.arange(-8, 9) for c in (1, 2)])
+        wl["long_mixed"] = workload_line("long", a.steps, a.warmup, extra_bins=alias,
+                                         tune_cache=a.tune_cache)
         wl["diff"] = gradient_timing(a.steps)
-        wl["stress_mixed"] = workload_line("stress", max(3, a.steps // 2), 2, parity_bins=192,
+        wl["stress_mixed"] = workload_line("stress", max(3, a.steps // 2), 2, parity_bins=448,
                                            tune_cache=a.tune_cache)
         torch.cuda.empty_cache()
         wl["stress_fp64"] = workload_line("stress", max(3, a.steps // 2), 2, precision="fp64",
-                                          parity_bins=192, tune_cache=a.tune_cache)
+                                          parity_bins=448, tune_cache=a.tune_cache)
         out["workloads"] = wl
     if not a.no_extras:
         torch.cuda.empty_cache()
