@@ -162,8 +162,9 @@ typedef struct {
                                 support fchi2_search, fchi2_search_curves,
                                 fchi2_autotune and fchi2_search_top (ln p
                                 with the bin index k0 + k of the search; idx,
-                                chi2_best and dchi2_adj per band; a band's
-                                first and last bins are never candidates), not
+                                chi2_best and dchi2_adj per band; the bin
+                                beyond each end of the band is solved too, so
+                                the band's first and last bins are ranked), not
                                 backward, shared alpha or floor gridding      */
   double oversampling;       /* os for n_freq = 0 (0 = default 5); > 0       */
   const double* t_span;      /* host [n_curves]: each curve's time span
@@ -355,7 +356,9 @@ fchi2_status_t fchi2_top_peaks(fchi2_plan_t plan, const void* dchi2, int32_t hro
  * Candidates are the strict local maxima D[k] > D[k-1], D[k] >= D[k+1] of row
  * hrow over the eligible bins: k >= max(k_lo, 1), f_k >= 1/span (no
  * FCHI2_BIN_LOW_F flag) and k <= n_freq - 2; ties in ln p go to the lower k.
- * The Delta chi2 values are exactly those fchi2_search writes (same rounding),
+ * Band plans (first_bin > 0) also solve the bin before their first and the
+ * bin after their last, so there every bin k >= k_lo is eligible, the first
+ * and last compared with those outside neighbours.  The Delta chi2 values are exactly those fchi2_search writes (same rounding),
  * so both select the same bins.  Also returns the adjusted reduction
  *     Delta chi2_adj = Delta chi2 * N_dof / chi2_best,
  * with chi2_best = chi2_0 - (largest Delta chi2 of row hrow over the eligible

@@ -15,7 +15,8 @@
 // (NaN when N_dof <= 0).
 //
 // Candidates are the strict local maxima D[k] > D[k-1], D[k] >= D[k+1] of
-// row hrow over eligible bins (k >= k_lo, k >= 1, f_k >= 1/span, k <= n_freq-2),
+// row hrow over eligible bins (k >= k_lo, k >= 1, f_k >= 1/span, k <= n_freq-2;
+// band plans: every k >= k_lo, with one bin beyond each end solved as well),
 // ranked by ln p ascending with ties to the lower k.  chi2_best uses the
 // largest Delta chi2 of row hrow over all eligible bins (k <= n_freq - 1).
 // The Delta chi2 values ranked are those the full search writes (rounded to
@@ -79,7 +80,10 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
   for (int r = 0; r < kBPT; ++r) {
     const int i = r * kNT + tid;
     const int64_t k = B0 - 1 + i;
-    if (k >= 0 && k < nf) {
+    // A band plan also solves the bins just outside its band (offsets
+    // -n_freq/2 - 1 and n_freq/2 from the centre, within the |o| < n_freq its
+    // spectra hold), so that its first and last bins can be ranked too.
+    if (BAND ? (k >= -1 && k <= nf) : (k >= 0 && k < nf)) {
       O d[H];
       const uint8_t fl = solve_bin<H, R, O, BAND>(zc, D, mo, g, cw, k, eps, d);
 #pragma unroll
@@ -92,7 +96,9 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
   __syncthreads();
 
   const int hp = hrow + 1;
-  const int64_t k_first = k_lo > 1 ? k_lo : 1;
+  // Band plans: bin 0 is bin k0 > 0 of the search.
+  const int64_t k_first = k_lo > (BAND ? 0 : 1) ? k_lo : (BAND ? 0 : 1);
+  const int64_t k_last = BAND ? nf - 1 : nf - 2;  // needs the bin after it
   const int lane = tid & 63, wv = tid >> 6;
   double vmax = -INFINITY;
   unsigned cand = 0;  // bit r: slot r * kNT + tid is a candidate
@@ -107,7 +113,7 @@ __global__ __launch_bounds__(kNT) void k_solve_top(
       if (eligible) {
         const double v = (double)s_d[hrow][i];
         if (v > vmax) vmax = v;  // NaN never raises the maximum
-        if (k <= nf - 2 && v > (double)s_d[hrow][i - 1] && v >= (double)s_d[hrow][i + 1])
+        if (k <= k_last && v > (double)s_d[hrow][i - 1] && v >= (double)s_d[hrow][i + 1])
           cand |= 1u << r;
       }
     }

@@ -76,13 +76,16 @@ def test_band_matches_oracle_and_the_full_search(precision, g):
     assert not np.any(fl_b[0] & F.BIN_DC)
 
 
-def _select(row, k0, df, span, hp, K):
+def _select(row, k0, df, span, hp, K, below, above):
     """The candidate rule applied to a band's written row: strict local maxima
-    inside the row (bins 1 .. n-2 of the band), f >= 1/span, ranked by
-    ln p = ln(k0 + j) + ln Q(D | 2hp) with the bin index of the search."""
+    of the search's Delta chi2 (the band's first and last bins compared with
+    the bins just outside the band, whose values are below and above),
+    f >= 1/span, ranked by ln p = ln(k0 + j) + ln Q(D | 2hp) with the bin index
+    of the search."""
     n = row.shape[0]
-    j = np.arange(1, n - 1)
-    j = j[((k0 + j) * df * span >= 1.0) & (row[j] > row[j - 1]) & (row[j] >= row[j + 1])]
+    ext = np.concatenate([[below], row, [above]])
+    j = np.arange(0, n)
+    j = j[((k0 + j) * df * span >= 1.0) & (ext[j + 1] > ext[j]) & (ext[j + 1] >= ext[j + 2])]
     u = 0.5 * np.maximum(row[j], 0.0)
     ssum = np.zeros_like(u)
     for q in range(hp):
@@ -106,13 +109,53 @@ def test_band_top_k_equals_the_selection_from_its_rows(precision):
     torch.cuda.synchronize()
     row = d[0, full.H - 1]
     span = float(full.t[-1] - full.t[0])
-    hi, hlp = _select(row, k0, full.f_max / full.n_freq, span, full.H, K)
+    df = full.f_max / full.n_freq
+    halo = ora.dchi2(*full.curve(0), np.array([k0 - 1, k0 + nb]) * df, full.H)["dchi2"]
+    hi, hlp = _select(row, k0, df, span, full.H, K, halo[-1, 0], halo[-1, 1])
     gi = r["idx"][0].cpu().numpy()
     glp = r["log_p"][0].cpu().numpy()
     print(f"band top-{K}: {gi[:4]} ln p {glp[:4]}", flush=True)
     assert list(gi) == list(hi)
     np.testing.assert_allclose(glp, hlp, rtol=1e-12, atol=1e-12)
     np.testing.assert_array_equal(r["dchi2"][0].cpu().numpy().T, d[0][:, gi])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("edge", ["first", "last"])
+def test_band_top_k_ranks_its_edge_bins(precision, edge):
+    """A band plan also solves the bin just outside each end of its band, so
+    a peak on its first or last bin is a candidate: a noiseless sinusoid whose
+    frequency is that bin's (no subharmonic of it lies in the band) is the
+    band's best candidate, with the ln p of its written row, and the oracle
+    puts the bin outside the band below it."""
+    import torch
+    g, K = 1, 4
+    n_freq, f_max = 2 ** 14, 10.0
+    nb = n_freq // G
+    k0 = g * nb
+    df = f_max / n_freq
+    ke = 0 if edge == "first" else nb - 1
+    rng = np.random.default_rng(41)
+    t = np.sort(rng.uniform(0.0, 100.0, 400))
+    s = rng.uniform(0.05, 0.2, 400)
+    x = 0.5 * np.sin(2 * np.pi * (k0 + ke) * df * t + 0.3) + 1e-4 * s * rng.standard_normal(400)
+    cur = synth.Curves(t=t, x=x, sigma=s, offsets=np.array([0, 400], dtype=np.int64), H=3,
+                       n_freq=n_freq, f_max=f_max, precision=precision, name="edge", meta={})
+    note(f"band {g} of {G} top-{K}, peak on its {edge} bin, {precision}")
+    d, _, _, plan = _band_search(cur, precision, g)
+    tt, xx, ss = to_dev(cur)
+    r = plan.search_top(tt, xx, ss, K=K)
+    torch.cuda.synchronize()
+    gi = r["idx"][0].cpu().numpy()
+    glp = r["log_p"][0].cpu().numpy()
+    print(f"band {edge}-bin peak: top {gi} ln p {glp}", flush=True)
+    assert gi[0] == ke
+    row = d[0, cur.H - 1]
+    out = k0 - 1 if edge == "first" else k0 + nb
+    ref = ora.dchi2(t, x, s, np.array([out, k0 + ke]) * df, cur.H)["dchi2"][-1]
+    assert ref[0] < ref[1] and row[ke] > ref[0] * (1 + 1e-4)
+    _, lp = _select(row[ke:ke + 1], k0 + ke, df, 100.0, cur.H, 1, -np.inf, -np.inf)
+    np.testing.assert_allclose(glp[0], lp[0], rtol=1e-12)
 
 
 def test_band_plan_refuses_what_it_does_not_support():
@@ -162,8 +205,11 @@ def test_band_top_k_lists_merge_into_the_full_search_top_k():
     """The all-gather step of a band split, run band after band on one GPU:
     the K best of each band (band 0 an ordinary plan of n_freq / G bins, the
     others band plans), merged by (ln p, bin), equal the K best of the search
-    over the whole range once the band-edge bins, which no band can rank
-    (their neighbours lie in the next band), are left out."""
+    over the whole range.  Band plans solve the bin beyond each end of their
+    band, so they rank their edge bins; two bins are left out of the
+    comparison: the last bin of band 0 (an ordinary plan, which has no bin
+    past its grid) and the last bin of the whole range (which the full search
+    cannot rank, but band G-1 can)."""
     import torch
     full = synth.make("plain", n=400, n_freq=2 ** 14, f_max=10.0)
     K = 12
@@ -173,7 +219,7 @@ def test_band_top_k_lists_merge_into_the_full_search_top_k():
     plan = F.Plan(full.offsets, full.f_max, full.H, full.n_freq, precision="fp64")
     rf = plan.search_top(t, x, s, K=2 * K)
     torch.cuda.synchronize()
-    edges = {g * nb for g in range(G)} | {g * nb + nb - 1 for g in range(G)}
+    edges = {nb - 1, G * nb - 1}
     fb = [int(b) for b in rf["idx"][0].cpu().numpy() if b >= 0 and int(b) not in edges][:K]
     flp = {int(b): v for b, v in zip(rf["idx"][0].cpu().numpy(), rf["log_p"][0].cpu().numpy())}
     cand = []
@@ -183,7 +229,7 @@ def test_band_top_k_lists_merge_into_the_full_search_top_k():
         r = bp.search_top(t, x, s, K=K)
         torch.cuda.synchronize()
         for j, lp in zip(r["idx"][0].cpu().numpy(), r["log_p"][0].cpu().numpy()):
-            if j >= 0:
+            if j >= 0 and g * nb + int(j) not in edges:
                 cand.append((float(lp), g * nb + int(j)))
     merged = sorted(cand)[:K]
     mb = [b for _, b in merged]
