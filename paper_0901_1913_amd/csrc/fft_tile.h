@@ -349,15 +349,25 @@ __device__ __forceinline__ void spread_into_tile(const FftPassArgs& a, const Mom
 // with r, c built per workgroup in FP64 and small[e] = w_L^e, e < N T.
 // LDS of one tile: the data tile, the row and column twiddles and, in the
 // first pass, the output offset of each tile column.
+// FP64 tiles keep the row twiddles in the padding column of the data tile
+// (one 16-byte slot per row that no data access touches), which brings the
+// 2^9 x 8 tile from 82 to 74 KB: two workgroups per CU instead of one.
 template <typename S, int LOGN, int LOGT>
 struct FftSmem {
   static constexpr int N = 1 << LOGN;
   static constexpr int T = 1 << LOGT;
   static constexpr int PT = (T == 1) ? 1 : T + 1;
+  static constexpr bool kTrInPad = sizeof(cplx<S>) == sizeof(C) && T > 1;
   __align__(16) cplx<S> sm[N * PT];
-  C tr[T == 1 ? 1 : N];  // the single-pass tile has no twiddles
+  C tr[(T == 1 || kTrInPad) ? 1 : N];  // the single-pass tile has no twiddles
   C tc[T];
   int64_t s_rev[T];
+  __device__ __forceinline__ C& row_tw(int k) {
+    if constexpr (kTrInPad)
+      return *reinterpret_cast<C*>(&sm[k * PT + T]);
+    else
+      return tr[k];
+  }
 };
 
 // One tile of one pass: columns [bx T, bx T + T) of packed grid p of wave slot
@@ -380,7 +390,6 @@ __device__ __forceinline__ void fft_pass_tile(const FftPassArgs& a, const cplx<S
   using S0 = Stage<LOGN, LOGT, 0>;
   using SL = Stage<LOGN, LOGT, last_logns(LOGN)>;
   cplx<S>* sm = sh.sm;
-  C* tr = sh.tr;
   C* tc = sh.tc;
   int64_t* s_rev = sh.s_rev;
 
@@ -443,9 +452,9 @@ __device__ __forceinline__ void fft_pass_tile(const FftPassArgs& a, const cplx<S
         for (int d = 1; d < np - 1; ++d) bits_below += a.logn[d];
         const int64_t jd = g0 >> bits_below;
         const int64_t Mmask = ((int64_t)1 << logM) - 1;
-        for (int k = tid; k < N; k += kNT) tr[k] = root((jd * k) & Mmask, logM);
+        for (int k = tid; k < N; k += kNT) sh.row_tw(k) = root((jd * k) & Mmask, logM);
       } else {
-        for (int k = tid; k < N; k += kNT) tr[k] = root((g0 * k) & (L - 1), logL);
+        for (int k = tid; k < N; k += kNT) sh.row_tw(k) = root((g0 * k) & (L - 1), logL);
       }
     }
   } else {
@@ -467,7 +476,7 @@ __device__ __forceinline__ void fft_pass_tile(const FftPassArgs& a, const cplx<S
       const int logTail = logL - low_bits - LOGN;
       const int logM = a.logn[a.q - 1] + LOGN + logTail;
       const int64_t Mmask = ((int64_t)1 << logM) - 1;
-      for (int k = tid; k < N; k += kNT) tr[k] = root((jd * Tail * k) & Mmask, logM);
+      for (int k = tid; k < N; k += kNT) sh.row_tw(k) = root((jd * Tail * k) & Mmask, logM);
       for (int cc = tid; cc < T; cc += kNT) tc[cc] = root((jd * (K0 + cc)) & Mmask, logM);
     }
   }
@@ -487,7 +496,7 @@ __device__ __forceinline__ void fft_pass_tile(const FftPassArgs& a, const cplx<S
 #pragma unroll
       for (int i = 0; i < SL::RAD; ++i) {
         const int k = SL::out_row(b, i);
-        C tw = tr[k];
+        C tw = sh.row_tw(k);
         if (np == 2) tw = cmul(tw, tw_small[cc * k]);
         sm[k * PT + cc] = narrow<S>(cmul(v[it * SL::RAD + i], tw));
       }
@@ -523,7 +532,7 @@ __device__ __forceinline__ void fft_pass_tile(const FftPassArgs& a, const cplx<S
 #pragma unroll
       for (int i = 0; i < SL::RAD; ++i) {
         const int k = SL::out_row(b, i);
-        nts<NT>(&base[(int64_t)k * Tail + cc], narrow<S>(cmul(v[it * SL::RAD + i], cmul(fc, tr[k]))));
+        nts<NT>(&base[(int64_t)k * Tail + cc], narrow<S>(cmul(v[it * SL::RAD + i], cmul(fc, sh.row_tw(k)))));
       }
     }
   } else {
@@ -561,9 +570,20 @@ __device__ __forceinline__ void fft_pass_tile(const FftPassArgs& a, const cplx<S
   }
 }
 
+// Waves per SIMD a pass kernel is compiled for.  FP32 tiles of 8192
+// elements are workgroups of eight waves with 72-78 KB of LDS, two per CU,
+// which needs four waves per SIMD (at most 128 registers): left to itself the
+// compiler gives the 2^9-row tiles 130 registers and the CU one workgroup
+// (stress workload: FFT 9.3 -> 8.1 ms).  The fused first pass (spreading
+// inside the tile) keeps its own allocation: at 128 registers it spills.
+template <typename S, bool FUSED>
+constexpr int fft_pass_waves() {
+  return (sizeof(S) == 4 && !FUSED) ? 4 : 1;
+}
+
 // The pass over a wave of curves: grid (column tiles, pairs, curves).
 template <typename S, int LOGN, int LOGT, bool FUSED>
-__global__ __launch_bounds__(((1 << LOGN) << LOGT) / kEPT) void k_fft_pass(
+__global__ __launch_bounds__(((1 << LOGN) << LOGT) / kEPT, (fft_pass_waves<S, FUSED>())) void k_fft_pass(
     FftPassArgs a, const cplx<S>* in, cplx<S>* out, const Moments* __restrict__ mom, Geom g,
     const C* __restrict__ tw_stage, const C* __restrict__ tw_small) {
   __shared__ FftSmem<S, LOGN, LOGT> sh;
