@@ -300,7 +300,8 @@ def peak_and_low_bins(row, k_lo, n_peaks=32, halo=2, n_low=32):
 
 
 def workload_line(name, steps, warmup, precision=None, parity_bins=2048, seed=11,
-                  extra_bins=None, schedule=None, tune_cache=None, full_grid=False):
+                  extra_bins=None, schedule=None, tune_cache=None, full_grid=False,
+                  parity=True):
     """Timing (autotuned, or on the given schedule), stage split, roofline and
     oracle parity of one single-curve workload: on every bin (full_grid), or
     on parity_bins seeded bins, the 32 highest local maxima of the H row +-2,
@@ -338,6 +339,16 @@ def workload_line(name, steps, warmup, precision=None, parity_bins=2048, seed=11
     roof["traffic"] = None if tr is None else int(round(tr))  # one curve per launch
     ms_median = _LAST_MEDIAN["ms"]
     units = cur.n_freq * cur.H
+    line = {"workload": name, "n": int(cur.t.shape[0]), "H": cur.H, "n_freq": cur.n_freq,
+            "f_max": cur.f_max, "precision": prec, "ms_per_search": round(ms, 5),
+            "ms_median": round(ms_median, 5),
+            "wall_ms_per_search": round(wall, 5), "value": round(units / (ms * 1e-3), 1),
+            "unit": "freq*H/s", "schedule": schedule, "autotune_s": round(tune_s, 2),
+            "stages_ms": stage_ms, "roofline": roof, "sections": sections}
+    if not parity:  # profiling runs: the GPU part only
+        plan.close()
+        log(f"{name} {prec}: {ms:.4f} ms/search (no parity check)")
+        return line
     # Parity bins (oracle on the host's CPU share).
     span = float(cur.t[-1] - cur.t[0])
     k_lo = int(np.ceil(cur.n_freq / (span * cur.f_max)))
@@ -380,12 +391,7 @@ def workload_line(name, steps, warmup, precision=None, parity_bins=2048, seed=11
                            + (", extra bins" if extra_bins is not None else ""))})
     log(f"{name} {prec}: {ms:.4f} ms/search, parity max {par['max_rel_err_gated']:.3e} "
         f"on {len(bins)} bins")
-    return {"workload": name, "n": int(cur.t.shape[0]), "H": cur.H, "n_freq": cur.n_freq,
-            "f_max": cur.f_max, "precision": prec, "ms_per_search": round(ms, 5),
-            "ms_median": round(ms_median, 5),
-            "wall_ms_per_search": round(wall, 5), "value": round(units / (ms * 1e-3), 1),
-            "unit": "freq*H/s", "schedule": schedule, "autotune_s": round(tune_s, 2),
-            "stages_ms": stage_ms, "roofline": roof, "sections": sections, "parity": par,
+    return {**line, "parity": par,
             "oracle": {"value": round(len(bins) * cur.H / el, 2), "cores": cores,
                        "bins": int(len(bins)), "wall_s": round(el, 2),
                        "full_grid_s": (round(el, 2) if full_grid else
@@ -646,6 +652,9 @@ def main(argv=None):
                     choices=["plain", "long", "diff", "stress"],
                     help="run only this workload's line and print it (for profiling; "
                          "not the headline)")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="--workload-only: time and profile the GPU search without the "
+                         "oracle comparison (for profiler runs)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device copy of this many MiB (a known-size kernel "
                          "against which HBM counters are scaled)")
@@ -671,7 +680,7 @@ def main(argv=None):
         if a.calib_copy_mb > 0:
             calibration_copy(a.calib_copy_mb)
         line = workload_line(a.workload_only, a.steps, a.warmup, schedule=sched_arg,
-                             tune_cache=a.tune_cache)
+                             tune_cache=a.tune_cache, parity=not a.no_parity)
         print(json.dumps({"workload_only": line}), flush=True)
         return 0
     cur = synth.make("batch")
