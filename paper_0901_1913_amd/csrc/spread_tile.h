@@ -76,7 +76,81 @@ struct SpreadSmem {
   double s_p[kSpreadCH];   // cell coordinate relative to the tile start (exact)
   double2 s_v[kSpreadCH];  // strengths of the real and imaginary parts
   int s_first[kNT];
+  int s_first1[kNT];       // the second component's, when both are staged at once
 };
+
+// Point q of harmonic m (absolute index i) staged for a tile whose unwrapped
+// first cell is base: its cell coordinate relative to base and its strengths
+// (sre, sim) as the spreading adds them.
+template <bool BAND>
+__device__ __forceinline__ void stage_point(const double* __restrict__ t,
+                                            const double* __restrict__ x,
+                                            const double* __restrict__ sigma, const Moments& mo,
+                                            const Geom& g, int comp, int m, int kind_a,
+                                            int kind_b, bool both, int64_t i, int64_t base,
+                                            double* s_p, double2* s_v, int q) {
+  // floor gridding: pos is an integer and the kernel below is exp(0) = 1 at
+  // d = 0 and 0 at |d| >= 1 (w = 1)
+  const double pos = cell_pos(t, i, mo.T0, g.df, m, (double)g.L, (double)g.c_off, g.w == 1);
+  const double si = sigma[i];
+  const double w = 1.0 / (si * si);
+  const double wy = w * (x[i + mo.xshift] - mo.xbar);
+  const double sa = (kind_a == 0) ? w : wy;
+  double sre, sim;
+  if constexpr (BAND) {
+    // Band plan: strength times exp(+2 pi i kc m u), kc = k0 + n_freq/2 the
+    // band's middle bin, so that grid bin j (j - L for j >= L/2) is bin
+    // kc + j of the search.  The phase kc m u in cycles is reduced modulo 1
+    // from the FP64 product and its exact rounding residual.
+    const double km = (double)((g.k0 + g.n_freq / 2) * (int64_t)m);
+    const double u = (t[i] - mo.T0) * g.df;
+    const double ph = km * u;
+    const double r = fma(km, u, -ph);
+    double fr = (ph - floor(ph)) + r;
+    fr -= floor(fr);
+    double sn, cs;
+    sincospi(2.0 * fr, &sn, &cs);
+    sre = sa * cs;
+    sim = sa * sn;
+  } else if (comp == 0) {
+    sre = sa;
+    sim = both ? ((kind_b == 0) ? w : wy) : 0.0;
+  } else {
+    sre = 0.0;
+    sim = sa;
+  }
+  // pos - base is exact (a multiple of pos's ulp, smaller than pos), and so
+  // is jl - s_p below: the same kernel argument as jl - cell - frac.
+  s_p[q] = pos - (double)base;
+  s_v[q] = make_double2(sre, sim);
+}
+
+// First staged point in [lo, hi) with coordinate >= key (binary search).
+__device__ __forceinline__ int first_at_or_above(const double* s_p, int lo, int hi, double key) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (s_p[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Adds to cell jl (coordinate cl) the taps of the staged points [q, end)
+// within the kernel's reach, in index order.
+template <bool EXACT>
+__device__ __forceinline__ void add_taps(const double* s_p, const double2* s_v, int q, int end,
+                                         double cl, double hreach, double two_over_w,
+                                         double beta, double& ar, double& ai) {
+  while (q < end && cl - s_p[q] > hreach) ++q;
+  for (int r = q; r < end; ++r) {
+    const double d = cl - s_p[r];
+    if (d <= -hreach) break;
+    const double phi = es_kernel<EXACT>(d * two_over_w, beta);
+    const double2 v = s_v[r];
+    ar += phi * v.x;
+    ai += phi * v.y;
+  }
+}
 
 // One tile of B cells (tile `tile` of packed grid p) of the curve mo, whose
 // table rows are in slot cw (or slot 0 with share_tb), written to out (the
@@ -121,6 +195,70 @@ __device__ __forceinline__ void spread_tile(const double* __restrict__ t,
   // runs over g.laps periods, so the tile gathers its points lap after lap
   // (in index order: positions grow with t).
   const int64_t ntile = g.L >> LOGB;
+  const int SPC = B / kNT;  // cells per binary search
+  if constexpr (!BAND) {
+    // A pair of two distinct harmonics on one lap whose points fit the LDS
+    // chunk together: both components are staged in one round (one chain of
+    // table and point loads, three barriers instead of six).  Each cell adds
+    // component 0's taps, then component 1's, in index order, exactly as
+    // the component-by-component loop below does.
+    const int m0 = g.comp_m[p][0], m1 = g.comp_m[p][1];
+    if (g.laps == 1 && m0 != 0 && m1 != 0 && m1 != m0) {
+      const int32_t* row0 = tb + ((int64_t)(share_tb ? 0 : cw) * (2 * g.H) + (m0 - 1)) * ntb;
+      const int32_t* row1 = tb + ((int64_t)(share_tb ? 0 : cw) * (2 * g.H) + (m1 - 1)) * ntb;
+      const int64_t lim0 = tile_limit_of(t_last, mo, g, m0, LOGB);
+      const int64_t lim1 = tile_limit_of(t_last, mo, g, m1, LOGB);
+      int64_t lo0 = 0, lo1 = 0;
+      int cnt0 = 0, cnt1 = 0;
+      if (tile + 2 <= lim0) {
+        lo0 = pa + row0[tile];
+        const int64_t hi0 = pa + row0[tile + 2];
+        cnt0 = hi0 > lo0 ? (int)(hi0 - lo0) : 0;
+      }
+      if (tile + 2 <= lim1) {
+        lo1 = pa + row1[tile];
+        const int64_t hi1 = pa + row1[tile + 2];
+        cnt1 = hi1 > lo1 ? (int)(hi1 - lo1) : 0;
+      }
+      if ((int64_t)cnt0 + cnt1 <= CH) {
+        const int n01 = cnt0 + cnt1;
+        if (n01 > 0) {
+          const int kind0 = g.comp_kind[p][0], kind1 = g.comp_kind[p][1];
+          for (int q = tid; q < n01; q += kNT) {
+            if (q < cnt0)
+              stage_point<false>(t, x, sigma, mo, g, 0, m0, kind0, -1, false, lo0 + q, a0, s_p,
+                                 s_v, q);
+            else
+              stage_point<false>(t, x, sigma, mo, g, 1, m1, kind1, -1, false, lo1 + (q - cnt0),
+                                 a0, s_p, s_v, q);
+          }
+          __syncthreads();
+          {
+            const double key = (double)(tid * SPC - hw - 1);
+            s_first[tid] = first_at_or_above(s_p, 0, cnt0, key);
+            sh.s_first1[tid] = first_at_or_above(s_p, cnt0, n01, key);
+          }
+          __syncthreads();
+#pragma unroll
+          for (int u = 0; u < CPT; ++u) {
+            const int jl = tid + u * kNT;
+            const double cl = (double)jl;
+            double ar = acc_re[u], ai = acc_im[u];
+            add_taps<EXACT>(s_p, s_v, s_first[jl / SPC], cnt0, cl, hreach, two_over_w, beta, ar,
+                            ai);
+            add_taps<EXACT>(s_p, s_v, sh.s_first1[jl / SPC], n01, cl, hreach, two_over_w, beta,
+                            ar, ai);
+            acc_re[u] = ar;
+            acc_im[u] = ai;
+          }
+          __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) out[tid + u * kNT] = cmk<S>((S)acc_re[u], (S)acc_im[u]);
+        return;
+      }
+    }
+  }
   for (int comp = 0; comp < 2; ++comp) {
     const int m = g.comp_m[p][comp];
     if (m == 0) continue;
@@ -140,77 +278,23 @@ __device__ __forceinline__ void spread_tile(const double* __restrict__ t,
 
     for (int64_t ch = i_lo; ch < i_hi; ch += CH) {
       const int cnt = (int)((i_hi - ch) < CH ? (i_hi - ch) : CH);
-      for (int q = tid; q < cnt; q += kNT) {
-        const int64_t i = ch + q;
-        // floor gridding: pos is an integer and the kernel below is
-        // exp(0) = 1 at d = 0 and 0 at |d| >= 1 (w = 1)
-        const double pos = cell_pos(t, i, mo.T0, g.df, m, Ld, coff, g.w == 1);
-        const double si = sigma[i];
-        const double w = 1.0 / (si * si);
-        const double wy = w * (x[i + mo.xshift] - mo.xbar);
-        const double sa = (kind_a == 0) ? w : wy;
-        double sre, sim;
-        if constexpr (BAND) {
-          // Band plan: strength times exp(+2 pi i kc m u), kc = k0 + n_freq/2
-          // the band's middle bin, so that grid bin j (j - L for j >= L/2)
-          // is bin kc + j of the search.  The phase kc m u in cycles is
-          // reduced modulo 1 from the FP64 product and its exact rounding
-          // residual.
-          const double km = (double)((g.k0 + g.n_freq / 2) * (int64_t)m);
-          const double u = (t[i] - mo.T0) * g.df;
-          const double ph = km * u;
-          const double r = fma(km, u, -ph);
-          double fr = (ph - floor(ph)) + r;
-          fr -= floor(fr);
-          double sn, cs;
-          sincospi(2.0 * fr, &sn, &cs);
-          sre = sa * cs;
-          sim = sa * sn;
-        } else if (comp == 0) {
-          sre = sa;
-          sim = both ? ((kind_b == 0) ? w : wy) : 0.0;
-        } else {
-          sre = 0.0;
-          sim = sa;
-        }
-        // pos - base is exact (a multiple of pos's ulp, smaller than pos),
-        // and so is jl - s_p below: the same kernel argument as jl - cell - frac.
-        s_p[q] = pos - (double)base;
-        s_v[q] = make_double2(sre, sim);
-      }
+      for (int q = tid; q < cnt; q += kNT)
+        stage_point<BAND>(t, x, sigma, mo, g, comp, m, kind_a, kind_b, both, ch + q, base, s_p,
+                          s_v, q);
       __syncthreads();
       // Cell jl takes the points with floor(p) in [jl - hw - 1, jl + hw], i.e.
-      // jl - hw - 1 <= p < jl + hw + 1.  The first of them is found by binary
+      // jl - hw - 1 <= p < jl + hw + 1 (with d = jl - p the window is
+      // -(hw + 1) < d <= hw + 1).  The first of them is found by binary
       // search for every (B / 256)-th cell (one search per thread); cells in
       // between advance from it.
-      {
-        const int cs = tid * (B / kNT);
-        int lo = 0, hi = cnt;
-        const double key = (double)(cs - hw - 1);
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (s_p[mid] < key) lo = mid + 1;
-          else hi = mid;
-        }
-        s_first[tid] = lo;
-      }
+      s_first[tid] = first_at_or_above(s_p, 0, cnt, (double)(tid * SPC - hw - 1));
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < CPT; ++u) {
         const int jl = tid + u * kNT;
-        // with d = jl - p the window is -(hw + 1) < d <= hw + 1
-        const double cl = (double)jl;
-        int q = s_first[jl / (B / kNT)];
-        while (q < cnt && cl - s_p[q] > hreach) ++q;
         double ar = acc_re[u], ai = acc_im[u];
-        for (int r = q; r < cnt; ++r) {
-          const double d = cl - s_p[r];
-          if (d <= -hreach) break;
-          const double phi = es_kernel<EXACT>(d * two_over_w, beta);
-          const double2 v = s_v[r];
-          ar += phi * v.x;
-          ai += phi * v.y;
-        }
+        add_taps<EXACT>(s_p, s_v, s_first[jl / SPC], cnt, (double)jl, hreach, two_over_w, beta,
+                        ar, ai);
         acc_re[u] = ar;
         acc_im[u] = ai;
       }
