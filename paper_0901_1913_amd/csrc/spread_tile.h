@@ -179,6 +179,8 @@ __device__ __forceinline__ void spread_tile(const double* __restrict__ t,
   const double two_over_w = 2.0 / (double)g.w;
   const double hreach = (double)(hw + 1);
   const double beta = g.beta;
+  const double Ld = (double)g.L;
+  const double coff = (double)g.c_off;
   const int64_t pa = mo.start;
 
   double acc_re[CPT], acc_im[CPT];
