@@ -98,9 +98,10 @@ inline std::vector<FftPlan> fft_splits_uniform(int logL, int LE) {
   };
   // The extra pass pays only on short grids (at L = 2^18 three passes of 2^6
   // beat two of 2^9); on grids above 2^20 cells it is slower and each pass
-  // adds a rounding of the stored grid: measured on the stress workload
-  // (L = 2^26, mixed), every four-pass split gave 6.3e-6 to 1.4e-5 against
-  // the oracle where the three-pass splits gave 6.0e-6 to 9.9e-6.
+  // adds a rounding of the stored grid: measured on a curve of 1e6 points
+  // with H = 8 and 2^24 bins (L = 2^26, mixed), every four-pass split gave
+  // 6.3e-6 to 1.4e-5 against the oracle where the three-pass splits gave
+  // 6.0e-6 to 9.9e-6.
   const int np_max = logL > 20 ? best.np : best.np + 1;
   for (int np = best.np; np <= np_max && np <= kMaxPasses; ++np) {
     std::vector<FftPlan> found;
