@@ -574,8 +574,9 @@ __device__ __forceinline__ void fft_pass_tile(const FftPassArgs& a, const cplx<S
 // elements are workgroups of eight waves with 72-78 KB of LDS, two per CU,
 // which needs four waves per SIMD (at most 128 registers): left to itself the
 // compiler gives the 2^9-row tiles 130 registers and the CU one workgroup
-// (stress workload: FFT 9.3 -> 8.1 ms).  The fused first pass (spreading
-// inside the tile) keeps its own allocation: at 128 registers it spills.
+// (a curve of 1e6 points, H = 8, 2^24 bins: FFT 9.3 -> 8.1 ms).  The fused
+// first pass (spreading inside the tile) keeps its own allocation: at 128
+// registers it spills.
 template <typename S, bool FUSED>
 constexpr int fft_pass_waves() {
   return (sizeof(S) == 4 && !FUSED) ? 4 : 1;
