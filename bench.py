@@ -537,6 +537,68 @@ def gradient_timing(steps):
             "oracle": {"cores": cores, "bins": int(len(bins)), "wall_s": round(el, 2)}}
 
 
+def fine_timing(steps, K=16, R=64, levels=3, n_check=4):
+    """Fine search on the ungridded data (Section 3e) around the long curve's
+    K highest strict local maxima of the H row (fchi2_top_peaks on the
+    search's rows): `levels` zoom levels of R direct-sum trials each, timed
+    with events over the whole zoom; parity of the first level's rows against
+    the oracle at the same trial frequencies for n_check of the centres, and
+    of every centre's final best against the oracle at its frequency."""
+    import torch
+    from paper_0901_1913_amd import fchi2 as F
+    from paper_0901_1913_amd import synth
+    from oracle import fchi2_oracle as ora
+    cur = synth.make("long")
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision=cur.precision)
+    t = torch.from_numpy(cur.t).cuda()
+    x = torch.from_numpy(cur.x).cuda()
+    s = torch.from_numpy(cur.sigma).cuda()
+    d, _, _ = plan.search(t, x, s)
+    span = float(cur.t[-1] - cur.t[0])
+    df = cur.f_max / cur.n_freq
+    k_lo = int(np.ceil(1.0 / (span * df)))
+    idx = plan.top_peaks(d, cur.H - 1, k_lo, K)
+    fc = idx.double() * df
+    res = plan.refine(t, x, s, fc, levels=levels, R=R)  # warm-up
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        res = plan.refine(t, x, s, fc, levels=levels, R=R)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    lvl1 = plan.fine_search(t, x, s, fc, R=R, want_rows=True)
+    rows = lvl1["rows"][0, :n_check].double().cpu().numpy()      # [n_check, R, H]
+    fcn = fc[0].cpu().numpy()
+    r = np.arange(R, dtype=np.float64)
+    trials = np.concatenate([f + df * (2.0 * r / (R - 1) - 1.0) for f in fcn[:n_check]])
+    fb = res["f_best"][0].cpu().numpy()
+    db = res["dchi2_best"][0].cpu().numpy()                       # [K, H]
+    freqs = np.concatenate([trials, fb])
+    chunks = np.array_split(freqs, 4 * pool_size())
+    out, el, cores = oracle_pool([(cur.t, cur.x, cur.sigma, c, cur.H) for c in chunks if len(c)])
+    d_ora = np.concatenate([o[0] for o in out], axis=1)
+    kappa = np.concatenate([o[1] for o in out])
+    gpu = np.concatenate([rows.reshape(-1, cur.H).T, db.T], axis=1)
+    err = ora.rel_err(gpu, d_ora)
+    gate = (freqs >= 1.0 / span) & (kappa <= 1e6)
+    par = parity_summary([err], [gate])
+    par.update({"trials": int(len(trials)), "best": int(len(fb)),
+                "gate": "f >= 1/span, kappa <= 1e6 (direct sums in FP64)"})
+    plan.close()
+    n_trials = K * R * levels
+    log(f"fine search (long): {K} centres x {levels} levels x {R} trials in {ms:.4f} ms, "
+        f"parity max {par['max_rel_err_gated']:.3e}")
+    return {"workload": "long", "n": int(cur.t.shape[0]), "H": cur.H, "centres": K,
+            "levels": levels, "trials_per_level": R, "ms": round(ms, 5),
+            "value": round(n_trials * cur.H / (ms * 1e-3), 1), "unit": "trial freq*H/s",
+            "parity": par, "oracle": {"cores": cores, "freqs": int(len(freqs)),
+                                      "wall_s": round(el, 2)}}
+
+
 def variants_timing(steps):
     """The paper-faithful variants on the long workload: the search with floor
     gridding (kernel_width = 1, Section 3b) and the cubic detrending."""
@@ -847,6 +909,7 @@ def main(argv=None):
         torch.cuda.empty_cache()
         out["multi"] = multi_vs_curves(max(3, a.steps // 2))
         out["variants"] = variants_timing(a.steps)
+        out["fine"] = fine_timing(a.steps)
         out["band_share"] = band_share_timing(a.steps)
     print(json.dumps(out), flush=True)
     return 0
