@@ -566,6 +566,12 @@ def fine_timing(steps, K=16, R=64, levels=3, n_check=4):
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
+        plan.top_peaks(d, cur.H - 1, k_lo, K, out=idx)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_peaks = e0.elapsed_time(e1) / steps
+    e0.record(stream)
+    for _ in range(steps):
         res = plan.refine(t, x, s, fc, levels=levels, R=R)
     e1.record(stream)
     torch.cuda.synchronize()
@@ -594,6 +600,7 @@ def fine_timing(steps, K=16, R=64, levels=3, n_check=4):
         f"parity max {par['max_rel_err_gated']:.3e}")
     return {"workload": "long", "n": int(cur.t.shape[0]), "H": cur.H, "centres": K,
             "levels": levels, "trials_per_level": R, "ms": round(ms, 5),
+            "top_peaks_ms": round(ms_peaks, 5),
             "value": round(n_trials * cur.H / (ms * 1e-3), 1), "unit": "trial freq*H/s",
             "parity": par, "oracle": {"cores": cores, "freqs": int(len(freqs)),
                                       "wall_s": round(el, 2)}}
