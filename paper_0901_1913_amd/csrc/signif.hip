@@ -31,8 +31,8 @@
 // permutations, the owner of the winner advancing), and the four sorted wave
 // lists are merged by rank.  The K winners are written in order.  Phase 2:
 // the sorted per-block lists are merged in groups of up to 256 (one list per
-// thread, the same wave tournaments and rank merge), and the group lists once
-// more per curve, which gives the final K.
+// thread, the same wave tournaments and rank merge), and, where a curve has
+// more than one group, the group lists once more, which gives the final K.
 #include <cmath>
 #include <type_traits>
 #include <cstdint>
@@ -486,6 +486,16 @@ hipError_t launch_top_merge(const Moments* mom, const Geom& g, int curve0, int n
                             hipStream_t st) {
   const int nblk = top_blocks(g.n_freq);
   const int ng = top_groups(g.n_freq);
+  if (ng == 1) {
+    // At most 256 per-block lists per curve: one step merges them and writes
+    // the outputs (the same K smallest keys as two steps would keep).
+    hipLaunchKernelGGL(k_top_merge, dim3(1u, (unsigned)n_curves), dim3(kNT), 0, st,
+                       (const double*)sc.score, (const int64_t*)sc.k, (const int64_t*)nullptr,
+                       (const double*)sc.bmax, nblk, K, (double*)nullptr, (int64_t*)nullptr,
+                       (int64_t*)nullptr, (double*)nullptr, 1, mom, curve0, g.H, hrow,
+                       (const uint8_t*)sc.flag, (const double*)sc.d, out);
+    return hipGetLastError();
+  }
   // Groups of up to 256 per-block lists, then the group lists of each curve.
   hipLaunchKernelGGL(k_top_merge, dim3((unsigned)ng, (unsigned)n_curves), dim3(kNT), 0, st,
                      (const double*)sc.score, (const int64_t*)sc.k, (const int64_t*)nullptr,
