@@ -242,6 +242,7 @@ class Plan:
         st = _stream_handle(stream) if torch.cuda.is_available() else 0
         _check(lib().fchi2_plan(ctypes.byref(desc), ctypes.c_void_p(st), ctypes.byref(handle)))
         self._h = handle
+        self.offsets = off.copy()
         self.n_curves = off.shape[0] - 1
         self.n_total = int(off[-1])
         self.H, self.f_max = int(H), float(f_max)
@@ -664,18 +665,26 @@ def _make_autograd():
     class FChi2Fn(torch.autograd.Function):
         """Delta chi2 with the hand-written adjoint as its backward.
 
-        forward(t, x, sigma, plan) -> dchi2 [n_curves, H, n_freq]; the plan
-        must have keep_for_backward=True.  backward returns gradients for x
-        and sigma (t is not differentiated).
+        forward(t, x, sigma, plan, sort=False) -> dchi2 [n_curves, H, n_freq];
+        the plan must have keep_for_backward=True.  With sort=True the points
+        of each curve are first put in time order (the library itself flags
+        an unsorted curve and gives it NaN rows), and the gradients are
+        returned in the caller's order.  backward returns gradients for x and
+        sigma (t is not differentiated).
         """
 
         @staticmethod
-        def forward(ctx, t, x, sigma, plan):
+        def forward(ctx, t, x, sigma, plan, sort=False):
             if not plan.keep_for_backward:
                 raise ValueError("FChi2Fn needs a plan with keep_for_backward=True")
+            perm = None
+            if sort:
+                perm = time_order(plan.offsets, t)
+                t, x, sigma = t[perm], x[perm], sigma[perm]
             dchi2, _, _ = plan.search(t, x, sigma, want_flags=False)
             ctx.plan = plan
             ctx.generation = plan.generation()
+            ctx.perm = perm
             ctx.save_for_backward(t, x, sigma)
             return dchi2
 
@@ -685,9 +694,26 @@ def _make_autograd():
             plan = ctx.plan
             g = grad.to(plan.out_dtype).contiguous()
             gx, gs = plan.backward(t, x, sigma, g, generation=ctx.generation)
-            return None, gx, gs, None
+            if ctx.perm is not None:  # back to the caller's order
+                ux, us = torch.empty_like(gx), torch.empty_like(gs)
+                ux[ctx.perm] = gx
+                us[ctx.perm] = gs
+                gx, gs = ux, us
+            return None, gx, gs, None, None
 
     return FChi2Fn
+
+
+def time_order(offsets, t):
+    """Device permutation that puts the points of each curve (CSR offsets) in
+    ascending time, stably: t[perm] is sorted within every curve and the
+    curves keep their ranges."""
+    torch = _torch()
+    off = torch.as_tensor(np.asarray(offsets, dtype=np.int64), device=t.device)
+    counts = off[1:] - off[:-1]
+    curve = torch.repeat_interleave(torch.arange(counts.numel(), device=t.device), counts)
+    by_t = torch.argsort(t, stable=True)
+    return by_t[torch.argsort(curve[by_t], stable=True)]
 
 
 class _Lazy:

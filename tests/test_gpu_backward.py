@@ -135,3 +135,35 @@ def test_backward_of_an_older_forward_is_refused():
     d2[0, cur.H - 1, 100:200].sum().backward()
     torch.cuda.synchronize()
     assert torch.isfinite(x2.grad).all()
+
+
+def test_autograd_sorts_each_curve_and_returns_gradients_in_caller_order():
+    """FChi2Fn(..., sort=True) on points shuffled within each curve: the rows
+    equal those of the time-ordered input bit for bit and the gradients come
+    back in the caller's order; without the sort the shuffled curves are
+    flagged and get NaN rows."""
+    import torch
+    cur = synth.make("batch", n_curves=3, n_freq=2 ** 13, f_max=4.0, n_lo=200, n_hi=800)
+    note("autograd with per-curve time sort, 3 shuffled curves")
+    plan = F.Plan(cur.offsets, cur.f_max, cur.H, cur.n_freq, precision="mixed",
+                  keep_for_backward=True)
+    t, x, s = to_dev(cur)
+    rng = np.random.default_rng(5)
+    off = cur.offsets
+    perm = np.concatenate([a + rng.permutation(b - a) for a, b in zip(off[:-1], off[1:])])
+    pt = torch.from_numpy(perm).cuda()
+    Fn = F.fchi2_fn()
+    xr, sr = x.clone().requires_grad_(True), s.clone().requires_grad_(True)
+    d_ref = Fn.apply(t, xr, sr, plan)
+    d_ref[:, cur.H - 1, 100:300].sum().backward()
+    xq, sq = x[pt].clone().requires_grad_(True), s[pt].clone().requires_grad_(True)
+    d = Fn.apply(t[pt], xq, sq, plan, True)
+    d[:, cur.H - 1, 100:300].sum().backward()
+    torch.cuda.synchronize()
+    assert torch.equal(d.detach(), d_ref.detach())
+    assert torch.isfinite(xr.grad).all() and torch.isfinite(sr.grad).all()
+    assert torch.equal(xq.grad, xr.grad[pt]) and torch.equal(sq.grad, sr.grad[pt])
+    d_bad, _, fl = plan.search(t[pt], x[pt], s[pt])
+    torch.cuda.synchronize()
+    assert torch.isnan(d_bad).all()
+    assert (fl.cpu().numpy() & F.CURVE_UNSORTED).all()
