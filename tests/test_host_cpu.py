@@ -35,3 +35,23 @@ def test_no_gpu_means_an_error_not_a_fallback():
     r = _bench("--steps", "1", "--warmup", "0")
     assert r.returncode != 0 and r.stdout == ""
     assert "needs a GPU" in r.stderr
+
+
+def test_time_order_sorts_within_each_curve():
+    """The autograd wrapper's per-curve time order (a host-side tensor helper):
+    stable within each CSR range, curves keep their ranges, empty curves and
+    ties included."""
+    import numpy as np
+    import torch
+    from paper_0901_1913_amd import fchi2 as F
+    rng = np.random.default_rng(2)
+    off = np.array([0, 7, 7, 20, 21, 40])
+    t = torch.from_numpy(np.round(rng.uniform(0, 5, off[-1]), 1))  # many ties
+    p = F.time_order(off, t).numpy()
+    assert sorted(p.tolist()) == list(range(off[-1]))
+    tn = t.numpy()
+    for a, b in zip(off[:-1], off[1:]):
+        seg = p[a:b]
+        assert ((seg >= a) & (seg < b)).all()
+        want = a + np.argsort(tn[a:b], kind="stable")
+        assert np.array_equal(seg, want)
