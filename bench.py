@@ -9,13 +9,16 @@ per second.  The same search run as a loop of single-curve calls (the plain
 form, same kernels) is timed beside it.
 
 Prints one JSON line.  Beside the throughput it reports the roofline of the
-kernel that takes the most time (algorithmic bytes by the scope table's byte
-model per launch, over its average launch duration measured with HIP events
-on the search stream in a separate profiled pass), the same model for the
-gridding + FFT stages and for the whole step, the FP64 solve rate, the FP64
-CPU oracle timed on a bounded sample of the batch (whose values double as a
-parity check), and one line per other workload (plain FP64, long curve,
-differentiation, precision stress in mixed and FP64).
+kernel that takes the most time (algorithmic bytes per launch: 3H real grids
+of 4 or 8 bytes per cell, a full FFT pass reading and writing each once;
+over its average launch duration measured with HIP events on the search
+stream in a separate profiled pass), the same model for the gridding + FFT
+stages and for the whole step, the FP64 solve rate, the FP64 CPU oracle
+timed on a bounded sample of the batch (whose values double as a parity
+check), one line per other workload (plain FP64, long curve,
+differentiation, precision stress in mixed and FP64), and extras: the fused
+top-16 search, shared-alpha sources, floor gridding and detrending, the
+fine search around the long curve's peaks, and frequency-band shares.
 """
 from __future__ import annotations
 
@@ -50,9 +53,9 @@ def cpu_model():
     return "unknown"
 
 
-def sec8d_bytes(n, H, n_freq, b, o):
-    """Algorithmic bytes per curve, by the scope table's model for the
-    HBM-grid schedule (3H real grids of L = 4 n_freq cells of b bytes, a
+def model_bytes(n, H, n_freq, b, o):
+    """Algorithmic bytes per curve, by the byte model of the HBM-grid
+    schedule (3H real grids of L = 4 n_freq cells of b bytes, a
     two-pass FFT with an output-pruned last pass, o-byte outputs):
     inputs 24 n; spreading writes L; FFT pass 1 reads and writes L; the last
     pass reads L and writes 2 n_freq; the assembly reads 2 n_freq; output
@@ -66,14 +69,14 @@ def sec8d_bytes(n, H, n_freq, b, o):
 
 
 def solve_flops(H):
-    """FP64 flops per bin of assembly + prefix Cholesky (scope table):
+    """FP64 flops per bin of assembly + prefix Cholesky:
     d^3/3 + 2 d^2 + d (d + 1), d = 2H + 1."""
     d = 2 * H + 1
     return d ** 3 / 3 + 2 * d * d + d * (d + 1)
 
 
 def stage_roofline(cur, stages, steps_profiled, b, o, schedule):
-    """Per-stage bytes by the scope table's model and rates from a profiled
+    """Per-stage bytes by the byte model and rates from a profiled
     pass: the dominant kernel's roofline, the gridding + FFT and whole-step
     effective bandwidths, and the solve's FP64 rate.  Each FFT pass is a full
     read and write of the grids (a schedule with more than two passes moves
@@ -83,7 +86,7 @@ def stage_roofline(cur, stages, steps_profiled, b, o, schedule):
     step's bytes."""
     H, nf, nc = cur.H, cur.n_freq, cur.n_curves
     n_tot = int(cur.t.shape[0])
-    m = sec8d_bytes(n_tot / nc, H, nf, b, o)
+    m = model_bytes(n_tot / nc, H, nf, b, o)
     n_pass = len(schedule["fft_log_radices"])
     per_stage_bytes = {  # per search, all curves
         "spread": nc * (m["spread"]) + 24 * n_tot,
@@ -113,10 +116,10 @@ def stage_roofline(cur, stages, steps_profiled, b, o, schedule):
             "avg_launch_ms": round(avg_launch_ms, 5), "launches_per_step": launches[dom],
             "byte_model": "3H real grids x b bytes: a full pass reads and writes 2 L per grid"}
     sections = {
-        "gridding_fft": {"gb_per_step_sec8d": round(grid_gb, 2), "ms": round(fft_ms, 4),
+        "gridding_fft": {"gb_per_step_model": round(grid_gb, 2), "ms": round(fft_ms, 4),
                          "gbs": round(grid_gb / (fft_ms * 1e-3), 1),
                          "frac": round(grid_gb / (fft_ms * 1e-3) / HBM_PEAK_GBS, 4)},
-        "whole_step": {"gb_per_step_sec8d": round(step_gb, 2), "ms": round(step_ms, 4),
+        "whole_step": {"gb_per_step_model": round(step_gb, 2), "ms": round(step_ms, 4),
                        "gbs": round(step_gb / (step_ms * 1e-3), 1),
                        "frac": round(step_gb / (step_ms * 1e-3) / HBM_PEAK_GBS, 4)},
     }
@@ -825,7 +828,7 @@ def main(argv=None):
     roof["stage_split"] = "one-stream plan on the timed schedule (kernels undisturbed)"
     # The whole step on the timed search itself (its spreading overlaps the
     # passes, so the stages' sum exceeds it).
-    ws_gb = sections["whole_step"]["gb_per_step_sec8d"]
+    ws_gb = sections["whole_step"]["gb_per_step_model"]
     sections["whole_step"].update({
         "ms": round(ms_step, 4), "gbs": round(ws_gb / (ms_step * 1e-3), 1),
         "frac": round(ws_gb / (ms_step * 1e-3) / HBM_PEAK_GBS, 4),
