@@ -533,7 +533,7 @@ fchi2_status_t fchi2_profile_read(fchi2_plan_t plan, double* total_ms, int64_t* 
  * wave_max/2, /4, /6, /8, /10, /12 curves with the last FFT pass and the
  * solve on whole or half waves, and for batches that fill the device the
  * persistent search; splits and tiles are ranked on the largest wave, wave
- * sizes for the three best of those) with HIP
+ * sizes for the best candidate of each of the three fastest splits) with HIP
  * events on `stream` (two timed runs each after a warm-up, then the three
  * fastest five more times each, in turns), keeps the fastest in the plan,
  * and appends it to the

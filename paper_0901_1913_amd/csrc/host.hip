@@ -688,9 +688,11 @@ fchi2_status_t check_ws(fchi2_plan_s* pl, void* ws, size_t bytes) {
 
 // Schedule search with `run`.  Stage 1 times every (FFT split, spreading
 // tile) on the largest wave (plus the fused first pass and the persistent
-// search where allowed); stage 2 times, for the three fastest of stage 1,
-// every wave size, each with the last pass and solve run on the whole wave
-// or on half-waves (allow_sub).  Each candidate runs 3 times (the first a
+// search where allowed); stage 2 times, for the fastest candidate of each of
+// the three fastest FFT splits of stage 1 (the best wave size differs between
+// splits: their passes share the CUs differently with the overlapped
+// spreading), every wave size, each with the last pass and solve run on the
+// whole wave or on half-waves (allow_sub).  Each candidate runs 3 times (the first a
 // warm-up, the faster of the other two kept); then the three fastest of all
 // run again, in turns, five times each, and the one with the lowest time is
 // returned: the first rounds rank, the last decides between close candidates
@@ -758,10 +760,19 @@ fchi2_status_t tune_loop(fchi2_plan_s* pl, const std::vector<FftPlan>& splits,
   if (res == FCHI2_OK && !cands.empty()) {
     std::stable_sort(cands.begin(), cands.end(), by_time);
     std::vector<TuneCand> more;
-    int taken = 0;
-    for (size_t i = 0; i < cands.size() && taken < 3; ++i) {
+    std::vector<FftPlan> taken;
+    auto same_split = [](const FftPlan& a, const FftPlan& b) {
+      if (a.np != b.np) return false;
+      for (int q = 1; q <= a.np; ++q)
+        if (a.logn[q] != b.logn[q] || a.le[q] != b.le[q]) return false;
+      return true;
+    };
+    for (size_t i = 0; i < cands.size() && taken.size() < 3; ++i) {
       if (cands[i].persist) continue;
-      ++taken;
+      bool seen = false;
+      for (const FftPlan& f : taken) seen = seen || same_split(f, cands[i].f);
+      if (seen) continue;
+      taken.push_back(cands[i].f);
       for (int wave : waves)
         for (int half = 0; half <= (allow_sub ? 1 : 0); ++half) {
           TuneCand c = cands[i];
